@@ -1,0 +1,151 @@
+/*
+ * tdbem.h -- C ABI of the MI355X time-domain CFIE boundary element library.
+ *
+ * Operation (T. Takahashi, "A fast time-domain boundary element method for
+ * three-dimensional electromagnetic scattering problems"):
+ *   The induced current J = n x H (n the inward normal) on a perfectly
+ *   conducting closed surface solves the CFIE  dL/dt(J) + theta eta (dK/dt(J) +
+ *   zeta K(J)) = tested incident field  (Section 2.1, Eq. cfie), discretised with
+ *   RWG bases in space and quadratic B-splines in time (Section 2.2) and
+ *   Galerkin-tested (Section 2.4).  Marching on in time (Section 2.5, Eqs. solve
+ *   and R) each step alpha solves
+ *       Zt^(1) J^{alpha-1} = V^{alpha-1} - sum_{g>=2} Zt^(g) J^{alpha-g},
+ *   where Zt^(g) are the coefficient matrices in the J-form (the paper's Jhat
+ *   form of Eq. layer_disc summed by parts; the MFIE identity term 1/2 J adds
+ *   1/2 theta eta Gram (1/dt + zeta/2) at g = 1 and (-1/dt + zeta/2) at g = 2).
+ *   In IFMM mode the history sum is split into near pairs (exact coefficients,
+ *   Program 2) and far pairs evaluated with the space-time interpolation-based
+ *   FMM (Section 3: P2M/M2L/L2P of Eqs. ddotA_M, ddotA_fmm, dotphi_fmm, P_fmm,
+ *   eval; M2M/L2L by re-interpolation; time gating of Programs 3-4).
+ *
+ * Conventions
+ *   Units are SI.  Every [N_e] array at this interface is in the canonical
+ *   RWG edge order: edges sorted lexicographically by (lo, hi) vertex index;
+ *   T+ is the triangle whose counter-clockwise (outward) vertex order runs
+ *   lo -> hi, T- the one running hi -> lo.  Batched arrays are [rhs][N_e]
+ *   (edge index fastest).  Device pointers are HIP device memory on the
+ *   current device; all work is stream-ordered on the stream given at setup.
+ *
+ * Ownership and errors
+ *   The caller owns every buffer it passes; the library copies the mesh and
+ *   never frees caller memory.  The context owns all device memory it
+ *   allocates and releases it in tdbem_destroy.  Every function returns 0 on
+ *   success or a negative TDBEM_E* code; tdbem_last_error() returns a
+ *   thread-local message for the last failure.  A context is not thread-safe.
+ */
+#ifndef TDBEM_H
+#define TDBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TDBEM_OK = 0,
+    TDBEM_EINVAL = -1,      /* invalid argument or mesh */
+    TDBEM_ENOMEM = -2,      /* device or host allocation failed */
+    TDBEM_EHIP = -3,        /* a HIP runtime call failed */
+    TDBEM_EBREAKDOWN = -4,  /* time hierarchy breaks down (steps per interval < 3, Remark 1) */
+    TDBEM_ENOCONV = -5,     /* GMRES did not reach the tolerance within the iteration cap */
+    TDBEM_EUNSTABLE = -6    /* current norm grew beyond the configured bound */
+};
+
+enum { TDBEM_MODE_DIRECT = 0, TDBEM_MODE_IFMM = 1 };
+enum { TDBEM_FP64 = 0, TDBEM_FP32 = 1, TDBEM_BF16 = 2 };
+enum { TDBEM_INTERP_LAGRANGE = 0 };
+enum { TDBEM_GUESS_EXTRAP = 0, TDBEM_GUESS_LEARNED = 1 };
+
+typedef struct tdbem_ctx tdbem_ctx;
+
+/* Closed, consistently (outward) oriented, manifold triangle mesh. */
+typedef struct {
+    int64_t n_vertices;
+    const double *xyz;        /* host [n_vertices][3], metres; copied */
+    int64_t n_triangles;
+    const int32_t *tri;       /* host [n_triangles][3], counter-clockwise seen from outside */
+} tdbem_mesh;
+
+typedef struct {
+    double dt;                /* time step [s] */
+    int32_t nt;               /* number of time steps the context may march */
+    int32_t d;                /* temporal B-spline order; must be 2 */
+    double eps, mu;           /* permittivity [F/m], permeability [H/m] */
+    double theta, zeta;       /* CFIE coupling constants (zeta in 1/s) */
+    int32_t p_s, p_t;         /* interpolation points per axis in space and in time (IFMM) */
+    int32_t interp;           /* TDBEM_INTERP_LAGRANGE (equispaced nodes) */
+    int32_t leaf_max;         /* subdivide a cell while it holds more edges than this */
+    int32_t min_level;        /* subdivide at least down to this level (2) */
+    int32_t mu_window;        /* far-field window (paper: 8 future intervals); raised if needed */
+    int32_t mode;             /* TDBEM_MODE_DIRECT (all pairs exact) or TDBEM_MODE_IFMM */
+    int32_t precision;        /* TDBEM_FP64 | TDBEM_FP32 | TDBEM_BF16 for near-field and M2L sums */
+    int32_t n_rhs;            /* independent incident fields marched together */
+    double gmres_rtol;        /* relative residual tolerance of the Z0 solve */
+    int32_t gmres_maxit;      /* Krylov iterations per step (cap) */
+    int32_t guess;            /* TDBEM_GUESS_EXTRAP (quadratic extrapolation) or _LEARNED */
+    void *stream;             /* hipStream_t for all work (NULL: the default stream) */
+} tdbem_config;
+
+/* Build the space-time hierarchy, the near-field J-form coefficients (computed
+ * on the device, FP64 semi-analytic inner integrals, 3-point testing), the Z0
+ * matrix and, in IFMM mode, the interpolation tables and M2L node values
+ * (Sections 2.3-2.5 and 3.4.1).  On success *out receives a new context.
+ * Errors: TDBEM_EINVAL (bad mesh/config), TDBEM_EBREAKDOWN (IFMM interval of
+ * fewer than 3 steps, Remark 1), TDBEM_ENOMEM, TDBEM_EHIP. */
+int tdbem_setup(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ctx **out);
+
+/* Tested incident field V^{step-1} (Eq. v_i) of n_rhs plane-wave pulses at
+ * t = step dt, written to V_dev [n_rhs][N_e] (device).  pulses: host array
+ * [n_rhs][11] = k(3), polarisation(3), E0, f0, sigma, delay, kind (0 modulated
+ * Gaussian cos(2 pi f0 tau) exp(-tau^2/2 sigma^2), 1 Sin^2 pulse of Section
+ * 4.1, 2 Gaussian of Section 4.3), tau = t - delay - k.x/c. */
+int tdbem_incident_planewave(tdbem_ctx *ctx, const double *pulses, int32_t step, double *V_dev);
+
+/* Stateless history evaluation.  hist_dev [n_hist][n_rhs][N_e] (device) holds
+ * J^0 .. J^{n_hist-1}; out_dev [n_rhs][N_e] (device) receives the history part
+ * of the right-hand side of step alpha = n_hist + 1:
+ *     sum_{g>=2} Zt^(g) J^{alpha-g}  (near pairs exact; far pairs by the IFMM
+ * replayed over the whole history in IFMM mode).  Resets the marching state. */
+int tdbem_potentials(tdbem_ctx *ctx, const double *hist_dev, int32_t n_hist, double *out_dev);
+
+/* One marching step: V_dev [n_rhs][N_e] = V^{alpha-1} in, J_dev [n_rhs][N_e] =
+ * J^{alpha-1} out (device); advances alpha.  TDBEM_ENOCONV if the Z0 solve
+ * misses the tolerance (the iterate is still returned). */
+int tdbem_step(tdbem_ctx *ctx, const double *V_dev, double *J_dev);
+
+/* Restart the march at alpha = 1 with zero history. */
+int tdbem_reset(tdbem_ctx *ctx);
+
+enum {
+    TDBEM_Q_NE = 0,          /* int64: number of edges */
+    TDBEM_Q_EDGES = 1,       /* int32 [N_e][2]: (lo, hi) vertex ids in canonical order */
+    TDBEM_Q_LMAX = 2,        /* int32: deepest octree level */
+    TDBEM_Q_MT = 3,          /* int32 [l_max+1]: steps per interval per level (0 above level 2) */
+    TDBEM_Q_NEAR_NNZ = 4,    /* int64: stored near-field coefficients (g >= 2) */
+    TDBEM_Q_NEAR_PAIRS = 5,  /* int64: near (i, j) pairs */
+    TDBEM_Q_Z0_NNZ = 6,      /* int64: non-zeros of Zt^(1) */
+    TDBEM_Q_NCELLS = 7,      /* int32 [l_max+1]: cells per level */
+    TDBEM_Q_NILIST = 8,      /* int64 [l_max+1]: interaction-list entries per level */
+    TDBEM_Q_WINDOW = 9,      /* int32: far-field source intervals per M2L (mu + 1) */
+    TDBEM_Q_GMRES_ITERS = 10,/* int32: Krylov iterations of the last step (max over rhs) */
+    TDBEM_Q_DEVICE_BYTES = 11,/* int64: device memory held by the context */
+    TDBEM_Q_STEP = 12,       /* int32: next step alpha */
+    TDBEM_Q_EDGE_LEAF = 13,  /* int32 [N_e]: internal (leaf-order) position of each canonical edge */
+    TDBEM_Q_SETUP_MS = 14    /* double: wall time of tdbem_setup */
+};
+int tdbem_query(const tdbem_ctx *ctx, int32_t key, void *out);
+
+/* Near-field coefficients of chosen rows (for tests): rows [n] canonical edge
+ * ids (host); out host [n][N_e][G] receives Zt^(g)_{row, j}, g = 0..G-1, for
+ * every stored near pair (zero elsewhere, g = 1 included). */
+int tdbem_near_rows(tdbem_ctx *ctx, const int32_t *rows, int32_t n, int32_t G, double *out);
+
+void tdbem_destroy(tdbem_ctx *ctx);
+const char *tdbem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDBEM_H */

@@ -273,7 +273,7 @@ static void tri_integrals(const double *x, const double P[3][3], int self, const
     double sa[ng], sphi[ng], sp[ng];              /* angular sums of Q(R) */
     double la[ng][3], lp[ng][3];                  /* boundary line sums of G m */
     for (int i = 0; i < ng; ++i) { sa[i] = sphi[i] = sp[i] = 0.0; for (int c = 0; c < 3; ++c) la[i][c] = lp[i][c] = 0.0; }
-    int inside = 1;
+    double theta_tot = 0.0;   /* total signed angle subtended by T at x0 */
     double br[4100];
     for (int e = 0; e < 3; ++e) {
         const double *A = P[e], *B = P[(e + 1) % 3], *Cv = P[(e + 2) % 3];
@@ -285,9 +285,10 @@ static void tri_integrals(const double *x, const double P[3][3], int self, const
         double bx[3]; sub3(B, x0, bx);
         double d = dot3(ax, m);                       /* >0 when x0 on the inner side */
         double sA = dot3(ax, t), sB = dot3(bx, t);
-        if (d <= 0.0) inside = 0;
-        /* ---- angular integral over the sub-triangle (x0, A, B) */
+        /* ---- angular integral over the sub-triangle (x0, A, B); a field point
+         * projecting onto the edge line gives a degenerate sub-triangle */
         if (fabs(d) > 1e-14 * L) {
+            theta_tot += atan(sB / d) - atan(sA / d);
             double ad = fabs(d), sg = d > 0 ? 1.0 : -1.0;
             double c2 = d * d + h * h;
             /* pieces in s split at 0 and at light-cone crossings */
@@ -343,24 +344,25 @@ static void tri_integrals(const double *x, const double P[3][3], int self, const
                 for (int c = 0; c < 3; ++c) { la[i][c] += la_e[i] * m[c]; lp[i][c] += lp_e[i] * m[c]; }
         }
     }
-    /* subtract Q(|h|) times the total subtended angle (2 pi inside, 0 outside) */
+    /* subtract Q(|h|) times the total subtended angle: 2 pi with the
+     * projection inside, 0 outside, pi on an edge, the corner angle at a vertex */
     double qa[ng], qphi[ng], qp[ng];
     for (int i = 0; i < ng; ++i) {
         acc[i].as = sa[i]; acc[i].phis = sphi[i]; acc[i].ps = sp[i];
     }
-    if (inside) {
-        if (ah > 0.0) {
-            radial_q(k, 0, ng, ah, qa, qphi, qp);
-            for (int i = 0; i < ng; ++i) { acc[i].as -= 2 * PI * qa[i]; acc[i].phis -= 2 * PI * qphi[i]; acc[i].ps -= 2 * PI * qp[i]; }
-        } else {
-            /* h = 0 inside: Qa(0), Qphi(0) finite; the psi integral only ever
-             * enters multiplied by h = 0 */
-            for (int i = 0; i < ng; ++i) {
-                double tau = (double)(k->g0 + i);
-                acc[i].as -= 2 * PI * (-k->cdt * bs1(tau));
-                acc[i].phis -= 2 * PI * (-k->cdt * bsm1(tau));
-                acc[i].ps = 0.0;
-            }
+    if (ah > 0.0) {
+        radial_q(k, 0, ng, ah, qa, qphi, qp);
+        for (int i = 0; i < ng; ++i) {
+            acc[i].as -= theta_tot * qa[i]; acc[i].phis -= theta_tot * qphi[i]; acc[i].ps -= theta_tot * qp[i];
+        }
+    } else {
+        /* h = 0: Qa(0), Qphi(0) finite; the psi integral only ever enters
+         * multiplied by h = 0 */
+        for (int i = 0; i < ng; ++i) {
+            double tau = (double)(k->g0 + i);
+            acc[i].as -= theta_tot * (-k->cdt * bs1(tau));
+            acc[i].phis -= theta_tot * (-k->cdt * bsm1(tau));
+            acc[i].ps = 0.0;
         }
     }
     for (int i = 0; i < ng; ++i) {

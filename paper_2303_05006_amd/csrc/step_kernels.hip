@@ -1,0 +1,349 @@
+// Per-step kernels of the marching-on-in-time loop (Program 1): the near-field
+// history sum sum_{g>=2} Zt^(g) J^{alpha-g} (Program 2, Eq. R), the Z0 GMRES
+// building blocks (Section 2.5), ring-buffer and boundary permutation helpers.
+//
+// Layouts: every per-edge state vector is [edge][rhs] (rhs fastest, leaf edge
+// order); the current history ring is [edge][slot][rhs] with slot = beta mod R,
+// so one pair's lag strip reads consecutive slots of one edge.
+#include <hip/hip_runtime.h>
+
+#include "tdbem_internal.h"
+
+namespace tdbem {
+
+// ---------------------------------------------------------------- near field
+// One 64-wide wavefront per target row; lanes stride over the row's pairs and
+// walk each pair's contiguous lag strip; butterfly reduction over the wave.
+template <typename VT>
+__global__ void __launch_bounds__(256) k_near_rhs1(int ne, const int *__restrict__ row_ptr, const int *__restrict__ pj,
+                                                   const int *__restrict__ pg0, const int *__restrict__ plen,
+                                                   const int64_t *__restrict__ poff, const VT *__restrict__ val,
+                                                   const double *__restrict__ ring, int ring_mask, int alpha,
+                                                   double *__restrict__ out, double scale_out) {
+    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (wave >= ne) return;
+    int R = ring_mask + 1;
+    double acc = 0.0;
+    for (int p = row_ptr[wave] + lane; p < row_ptr[wave + 1]; p += 64) {
+        int j = pj[p], g0 = pg0[p], len = plen[p];
+        const VT *v = val + poff[p];
+        const double *J = ring + (size_t)j * R;
+        int b = alpha - g0;
+        for (int l = 0; l < len; ++l) acc += (double)v[l] * J[(b - l) & ring_mask];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) out[wave] = scale_out * acc;
+}
+
+// batched right-hand sides: one wavefront per (row, 64-rhs group); lanes are rhs
+template <typename VT>
+__global__ void __launch_bounds__(256) k_near_rhsN(int ne, int nrhs, const int *__restrict__ row_ptr, const int *__restrict__ pj,
+                                                   const int *__restrict__ pg0, const int *__restrict__ plen,
+                                                   const int64_t *__restrict__ poff, const VT *__restrict__ val,
+                                                   const double *__restrict__ ring, int ring_mask, int alpha,
+                                                   double *__restrict__ out, double scale_out) {
+    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    int ngrp = (nrhs + 63) >> 6;
+    if (wave >= ne * ngrp) return;
+    int row = wave / ngrp, r = (wave % ngrp) * 64 + lane;
+    bool act = r < nrhs;
+    int R = ring_mask + 1;
+    double acc = 0.0;
+    for (int p = row_ptr[row]; p < row_ptr[row + 1]; ++p) {
+        int j = pj[p], g0 = pg0[p], len = plen[p];
+        const VT *v = val + poff[p];
+        const double *J = ring + (size_t)j * R * nrhs;
+        int b = alpha - g0;
+        if (act)
+            for (int l = 0; l < len; ++l) acc += (double)v[l] * J[(size_t)((b - l) & ring_mask) * nrhs + r];
+    }
+    if (act) out[(size_t)row * nrhs + r] = scale_out * acc;
+}
+
+void launch_near(const tdbem_ctx *C, int alpha, double *out, double scale, hipStream_t s) {
+    int bs = 256;
+    if (C->nrhs == 1) {
+        unsigned nb = (unsigned)(((int64_t)C->ne * 64 + bs - 1) / bs);
+        if (C->cfg.precision == TDBEM_FP64)
+            hipLaunchKernelGGL(k_near_rhs1<double>, dim3(nb), dim3(bs), 0, s, C->ne, C->d_nrow_ptr, C->d_npair_j, C->d_npair_g0,
+                               C->d_npair_len, C->d_npair_off, C->d_nval, C->d_Jring, C->ring - 1, alpha, out, scale);
+        else
+            hipLaunchKernelGGL(k_near_rhs1<float>, dim3(nb), dim3(bs), 0, s, C->ne, C->d_nrow_ptr, C->d_npair_j, C->d_npair_g0,
+                               C->d_npair_len, C->d_npair_off, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out, scale);
+    } else {
+        int ngrp = (C->nrhs + 63) / 64;
+        unsigned nb = (unsigned)(((int64_t)C->ne * ngrp * 64 + bs - 1) / bs);
+        if (C->cfg.precision == TDBEM_FP64)
+            hipLaunchKernelGGL(k_near_rhsN<double>, dim3(nb), dim3(bs), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_npair_j,
+                               C->d_npair_g0, C->d_npair_len, C->d_npair_off, C->d_nval, C->d_Jring, C->ring - 1, alpha, out, scale);
+        else
+            hipLaunchKernelGGL(k_near_rhsN<float>, dim3(nb), dim3(bs), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_npair_j,
+                               C->d_npair_g0, C->d_npair_len, C->d_npair_off, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out, scale);
+    }
+    TD_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------------------- helpers
+// canonical [rhs][ne] -> leaf [ne][rhs]
+__global__ void k_gather_in(int ne, int nrhs, const int *perm, const double *src, double *dst) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ne) return;
+    int e = perm[p];
+    for (int r = 0; r < nrhs; ++r) dst[(size_t)p * nrhs + r] = src[(size_t)r * ne + e];
+}
+// leaf [ne][rhs] -> canonical [rhs][ne]
+__global__ void k_scatter_out(int ne, int nrhs, const int *perm, const double *src, double *dst) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= ne) return;
+    int e = perm[p];
+    for (int r = 0; r < nrhs; ++r) dst[(size_t)r * ne + e] = src[(size_t)p * nrhs + r];
+}
+// y = a*x + b*y over n values
+__global__ void k_axpby(int64_t n, double a, const double *x, double b, double *y) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) y[k] = a * x[k] + b * y[k];
+}
+// ring slot write: ring[e][slot][r] = x[e][r]
+__global__ void k_ring_put(int ne, int nrhs, int R, int slot, const double *x, double *ring) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    int e = (int)(k / nrhs), r = (int)(k % nrhs);
+    ring[((size_t)e * R + slot) * nrhs + r] = x[k];
+}
+// quadratic extrapolation x = 3 J^{a-2} - 3 J^{a-3} + J^{a-4} (zero history before 0)
+__global__ void k_extrap(int ne, int nrhs, int R, int alpha, const double *ring, double *x) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    int e = (int)(k / nrhs), r = (int)(k % nrhs);
+    const double *J = ring + (size_t)e * R * nrhs + r;
+    auto at = [&](int b) { return b < 0 ? 0.0 : J[(size_t)(b & (R - 1)) * nrhs]; };
+    x[k] = 3.0 * at(alpha - 2) - 3.0 * at(alpha - 3) + at(alpha - 4);
+}
+
+// ------------------------------------------------------------------ GMRES
+// y = A x for a CSR matrix, [ne][rhs] vectors; one thread per (row, rhs)
+__global__ void k_spmv(int ne, int nrhs, const int *ptr, const int *col, const double *val, const double *x, double *y) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    int i = (int)(k / nrhs), r = (int)(k % nrhs);
+    double s = 0.0;
+    for (int q = ptr[i]; q < ptr[i + 1]; ++q) s += val[q] * x[(size_t)col[q] * nrhs + r];
+    y[k] = s;
+}
+// y = b - A x
+__global__ void k_resid(int ne, int nrhs, const int *ptr, const int *col, const double *val, const double *x,
+                        const double *b, double *y) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    int i = (int)(k / nrhs), r = (int)(k % nrhs);
+    double s = 0.0;
+    for (int q = ptr[i]; q < ptr[i + 1]; ++q) s += val[q] * x[(size_t)col[q] * nrhs + r];
+    y[k] = b[k] - s;
+}
+// y = Dinv .* x (Jacobi)
+__global__ void k_scale_rows(int ne, int nrhs, const double *dinv, const double *x, double *y) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    y[k] = dinv[k / nrhs] * x[k];
+}
+// partial dots: part[blk][m][r] = sum over this block's rows of V_m[e][r] * w[e][r]
+// V is nv vectors of size ne*nrhs, contiguous. Deterministic two-stage reduction.
+#define DOT_ROWS 256
+__global__ void k_mdot_part(int ne, int nrhs, int nv, const double *V, size_t vstride, const double *w, double *part) {
+    int blk = blockIdx.x, m = blockIdx.y;
+    int e0 = blk * DOT_ROWS;
+    __shared__ double sh[256];
+    for (int r = 0; r < nrhs; ++r) {
+        double s = 0.0;
+        for (int e = e0 + threadIdx.x; e < min(ne, e0 + DOT_ROWS); e += blockDim.x)
+            s += V[m * vstride + (size_t)e * nrhs + r] * w[(size_t)e * nrhs + r];
+        sh[threadIdx.x] = s;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[((size_t)blk * nv + m) * nrhs + r] = sh[0];
+        __syncthreads();
+    }
+}
+__global__ void k_mdot_final(int nblk, int nv, int nrhs, const double *part, double *out) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nv * nrhs) return;
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * nv * nrhs + k];
+    out[k] = s;
+}
+// w[e][r] -= sum_m h[m][r] V_m[e][r]
+__global__ void k_mupdate(int ne, int nrhs, int nv, const double *V, size_t vstride, const double *h, double *w) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    int r = (int)(k % nrhs);
+    double s = w[k];
+    for (int m = 0; m < nv; ++m) s -= h[m * nrhs + r] * V[m * vstride + k];
+    w[k] = s;
+}
+// V_out[e][r] = w[e][r] * s[r]
+__global__ void k_scale_rhs(int ne, int nrhs, const double *s, const double *w, double *v) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    v[k] = w[k] * s[k % nrhs];
+}
+// x += Dinv .* (sum_m y[m][r] V_m)
+__global__ void k_xupdate(int ne, int nrhs, int nv, const double *V, size_t vstride, const double *y,
+                          const double *dinv, double *x) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    int r = (int)(k % nrhs);
+    double s = 0.0;
+    for (int m = 0; m < nv; ++m) s += y[m * nrhs + r] * V[m * vstride + k];
+    x[k] += dinv[k / nrhs] * s;
+}
+
+static inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_gather_in(const tdbem_ctx *C, const double *src, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_in, dim3(nblk(C->ne, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->d_perm, src, dst);
+    TD_HIP(hipGetLastError());
+}
+void launch_scatter_out(const tdbem_ctx *C, const double *src, double *dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter_out, dim3(nblk(C->ne, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->d_perm, src, dst);
+    TD_HIP(hipGetLastError());
+}
+void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, s, n, a, x, b, y);
+    TD_HIP(hipGetLastError());
+}
+void launch_ring_put(const tdbem_ctx *C, int slot, const double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_ring_put, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, slot, x, C->d_Jring);
+    TD_HIP(hipGetLastError());
+}
+void launch_extrap(const tdbem_ctx *C, int alpha, double *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_extrap, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, alpha, C->d_Jring, x);
+    TD_HIP(hipGetLastError());
+}
+
+// Right-preconditioned (Jacobi) restarted GMRES on Z0 for every rhs in
+// lockstep; Arnoldi with classical Gram-Schmidt applied twice; Givens
+// rotations on the host.  Returns iterations used; sets *ok if every rhs
+// reached rtol relative to its right-hand-side norm.
+int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, bool *ok, hipStream_t s) {
+    const int ne = C->ne, nr = C->nrhs;
+    const int64_t n = (int64_t)ne * nr;
+    const int m = std::max(1, std::min(maxit, 30));
+    double *V = C->d_work;                       // (m+1) vectors
+    size_t vs = (size_t)n;
+    double *w = V + (size_t)(m + 1) * vs;
+    double *z = w + vs;
+    double *part = z + vs;                       // [nblk][m+1][nr]
+    double *dots = C->d_scal;                    // [(m+1) nr]
+    int nb = (ne + DOT_ROWS - 1) / DOT_ROWS;
+    unsigned g = nblk(n, 256);
+    std::vector<double> hd((size_t)(m + 1) * nr), bn(nr), beta(nr);
+    std::vector<double> H((size_t)(m + 1) * m * nr), cs((size_t)m * nr), sn((size_t)m * nr), gv((size_t)(m + 1) * nr);
+    auto mdot = [&](int nv, const double *Vb, const double *ww, double *host) {
+        hipLaunchKernelGGL(k_mdot_part, dim3(nb, nv), dim3(256), 0, s, ne, nr, nv, Vb, vs, ww, part);
+        hipLaunchKernelGGL(k_mdot_final, dim3(nblk(nv * nr, 256)), dim3(256), 0, s, nb, nv, nr, part, dots);
+        TD_HIP(hipMemcpyAsync(host, dots, sizeof(double) * nv * nr, hipMemcpyDeviceToHost, s));
+        TD_HIP(hipStreamSynchronize(s));
+    };
+    mdot(1, b, b, bn.data());
+    for (int r = 0; r < nr; ++r) bn[r] = std::sqrt(bn[r]);
+    int total = 0;
+    bool conv = false;
+    while (total < maxit) {
+        hipLaunchKernelGGL(k_resid, dim3(g), dim3(256), 0, s, ne, nr, C->d_z0_ptr, C->d_z0_col, C->d_z0_val, x, b, V);
+        mdot(1, V, V, beta.data());
+        bool all = true;
+        for (int r = 0; r < nr; ++r) {
+            beta[r] = std::sqrt(beta[r]);
+            if (!(beta[r] <= rtol * bn[r] || bn[r] == 0.0)) all = false;
+        }
+        if (all) { conv = true; break; }
+        std::vector<double> inv(nr);
+        for (int r = 0; r < nr; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+        TD_HIP(hipMemcpyAsync(dots, inv.data(), sizeof(double) * nr, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_scale_rhs, dim3(g), dim3(256), 0, s, ne, nr, dots, V, V);
+        std::fill(gv.begin(), gv.end(), 0.0);
+        for (int r = 0; r < nr; ++r) gv[r] = beta[r];
+        int k = 0;
+        for (; k < m && total < maxit; ++k, ++total) {
+            hipLaunchKernelGGL(k_scale_rows, dim3(g), dim3(256), 0, s, ne, nr, C->d_z0_dinv, V + k * vs, z);
+            hipLaunchKernelGGL(k_spmv, dim3(g), dim3(256), 0, s, ne, nr, C->d_z0_ptr, C->d_z0_col, C->d_z0_val, z, w);
+            std::vector<double> hsum((size_t)(k + 1) * nr, 0.0);
+            for (int pass = 0; pass < 2; ++pass) {
+                mdot(k + 1, V, w, hd.data());
+                TD_HIP(hipMemcpyAsync(dots, hd.data(), sizeof(double) * (k + 1) * nr, hipMemcpyHostToDevice, s));
+                hipLaunchKernelGGL(k_mupdate, dim3(g), dim3(256), 0, s, ne, nr, k + 1, V, vs, dots, w);
+                for (size_t q = 0; q < (size_t)(k + 1) * nr; ++q) hsum[q] += hd[q];
+            }
+            std::vector<double> hn(nr);
+            mdot(1, w, w, hn.data());
+            std::vector<double> inv2(nr);
+            for (int r = 0; r < nr; ++r) {
+                hn[r] = std::sqrt(hn[r]);
+                inv2[r] = hn[r] > 0 ? 1.0 / hn[r] : 0.0;
+            }
+            TD_HIP(hipMemcpyAsync(dots, inv2.data(), sizeof(double) * nr, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(k_scale_rhs, dim3(g), dim3(256), 0, s, ne, nr, dots, w, V + (k + 1) * vs);
+            bool all2 = true;
+            for (int r = 0; r < nr; ++r) {
+                double *Hc = &H[((size_t)r * (m + 1)) * m];   // column-major (m+1) x m per rhs
+                for (int q = 0; q <= k; ++q) Hc[q + (size_t)k * (m + 1)] = hsum[(size_t)q * nr + r];
+                Hc[k + 1 + (size_t)k * (m + 1)] = hn[r];
+                for (int q = 0; q < k; ++q) {
+                    double a = Hc[q + (size_t)k * (m + 1)], bb = Hc[q + 1 + (size_t)k * (m + 1)];
+                    double c = cs[(size_t)r * m + q], sgn = sn[(size_t)r * m + q];
+                    Hc[q + (size_t)k * (m + 1)] = c * a + sgn * bb;
+                    Hc[q + 1 + (size_t)k * (m + 1)] = -sgn * a + c * bb;
+                }
+                double a = Hc[k + (size_t)k * (m + 1)], bb = Hc[k + 1 + (size_t)k * (m + 1)];
+                double rr = std::hypot(a, bb);
+                double c = rr > 0 ? a / rr : 1.0, sgn = rr > 0 ? bb / rr : 0.0;
+                cs[(size_t)r * m + k] = c; sn[(size_t)r * m + k] = sgn;
+                Hc[k + (size_t)k * (m + 1)] = rr;
+                Hc[k + 1 + (size_t)k * (m + 1)] = 0.0;
+                double gk = gv[(size_t)k * nr + r];
+                gv[(size_t)k * nr + r] = c * gk;
+                gv[(size_t)(k + 1) * nr + r] = -sgn * gk;
+                if (!(std::fabs(gv[(size_t)(k + 1) * nr + r]) <= rtol * bn[r] || bn[r] == 0.0)) all2 = false;
+            }
+            if (all2) { ++k; ++total; break; }
+        }
+        // y = H^{-1} g (upper triangular k x k), x += Dinv V y
+        std::vector<double> y((size_t)k * nr, 0.0);
+        for (int r = 0; r < nr; ++r) {
+            double *Hc = &H[((size_t)r * (m + 1)) * m];
+            for (int q = k - 1; q >= 0; --q) {
+                double sacc = gv[(size_t)q * nr + r];
+                for (int t = q + 1; t < k; ++t) sacc -= Hc[q + (size_t)t * (m + 1)] * y[(size_t)t * nr + r];
+                double dgn = Hc[q + (size_t)q * (m + 1)];
+                y[(size_t)q * nr + r] = dgn != 0.0 ? sacc / dgn : 0.0;
+            }
+        }
+        TD_HIP(hipMemcpyAsync(dots, y.data(), sizeof(double) * k * nr, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_xupdate, dim3(g), dim3(256), 0, s, ne, nr, k, V, vs, dots, C->d_z0_dinv, x);
+        TD_HIP(hipGetLastError());
+    }
+    if (!conv) {
+        // final residual check after the last restart cycle
+        hipLaunchKernelGGL(k_resid, dim3(g), dim3(256), 0, s, ne, nr, C->d_z0_ptr, C->d_z0_col, C->d_z0_val, x, b, V);
+        mdot(1, V, V, beta.data());
+        conv = true;
+        for (int r = 0; r < nr; ++r)
+            if (!(std::sqrt(beta[r]) <= rtol * bn[r] * 1.0000001 || bn[r] == 0.0)) conv = false;
+    }
+    *ok = conv;
+    return total;
+}
+
+size_t gmres_work_doubles(const tdbem_ctx *C, int maxit) {
+    const int m = std::max(1, std::min(maxit, 30));
+    size_t n = (size_t)C->ne * C->nrhs;
+    int nb = (C->ne + DOT_ROWS - 1) / DOT_ROWS;
+    return (size_t)(m + 3) * n + (size_t)nb * (m + 1) * C->nrhs + 64;
+}
+
+}  // namespace tdbem

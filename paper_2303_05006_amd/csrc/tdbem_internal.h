@@ -1,0 +1,143 @@
+// Internal declarations of the MI355X TDBEM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/tdbem.h"
+
+namespace tdbem {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+struct Error {
+    int code;
+    std::string msg;
+};
+#define TD_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t _e = (call);                                                          \
+        if (_e != hipSuccess)                                                            \
+            throw ::tdbem::Error{TDBEM_EHIP, std::string(#call) + ": " + hipGetErrorString(_e)}; \
+    } while (0)
+#define TD_REQUIRE(cond, code, msg)                                                      \
+    do {                                                                                 \
+        if (!(cond)) throw ::tdbem::Error{code, msg};                                    \
+    } while (0)
+
+// ------------------------------------------------------------ host geometry
+struct HostMesh {
+    int nv = 0, nt = 0, ne = 0;
+    std::vector<double> xyz;        // [nv][3]
+    std::vector<int> tri;           // [nt][3]
+    // canonical edge order
+    std::vector<int> edge_v;        // [ne][2] (lo, hi)
+    std::vector<int> etri;          // [ne][2] T+, T-
+    std::vector<int> efree;         // [ne][2] o+, o-
+    std::vector<double> elen;       // [ne]
+    std::vector<int> tedge;         // [nt][3]
+    std::vector<double> area;       // [nt]
+    std::vector<double> nrm;        // [nt][3] outward unit normal
+    std::vector<double> qpt;        // [nt][3][3] interior 3-point rule points
+};
+
+// octree level data (cells of one level, in Morton order)
+struct Level {
+    int n = 0;
+    std::vector<int> ix, iy, iz;    // integer cell coordinates at this level
+    std::vector<int> parent;        // index at level-1 (-1 at level 0)
+    std::vector<int> child_beg, child_end;  // children index range at level+1
+    std::vector<int> ebeg, eend;    // edge range in leaf order
+    std::vector<char> leaf;
+    std::vector<int> nbr_off, nbr;  // neighbour list (Chebyshev distance <= 1, incl. self)
+    std::vector<int> il_off, il_src, il_code;  // interaction list: source cell, offset code
+};
+
+struct Tree {
+    double origin[3] = {0, 0, 0};
+    double side = 0;
+    int lmax = 0;
+    std::vector<Level> lev;         // 0..lmax
+    std::vector<int> perm;          // leaf position -> canonical edge id
+    std::vector<int> iperm;         // canonical edge id -> leaf position
+    std::vector<int> edge_leaf_level, edge_leaf_cell;  // per leaf-order edge
+};
+
+void build_mesh(const tdbem_mesh *m, HostMesh &H);
+void build_tree(const HostMesh &H, int leaf_max, int min_level, Tree &T);
+// near source cell lists per leaf cell (as (level, cell) pairs), Program 2
+void near_source_cells(const Tree &T, int level, int cell, std::vector<std::pair<int, int>> &out);
+
+// geometry view passed to device kernels (edges in leaf order)
+struct GeoDev {
+    const double *xyz; const int *tri; const double *area; const double *nrm; const double *qpt;
+    const int *etri; const int *efree; const double *elen;
+    double cdt, dt, eps, mu, theta, zeta, eta;
+};
+
+struct FarState;  // IFMM device state (ifmm.hip)
+
+}  // namespace tdbem
+
+struct tdbem_ctx {
+    tdbem_config cfg;
+    hipStream_t stream = nullptr;
+    tdbem::HostMesh H;
+    tdbem::Tree T;
+    int ne = 0, nrhs = 1;
+    double c = 0, eta = 0, cdt = 0;
+    int alpha = 1;                  // next step
+    int ring = 64;                  // history ring length (power of two)
+    int last_iters = 0;
+    double setup_ms = 0;
+    size_t dev_bytes = 0;
+    std::vector<void *> allocs;
+
+    // geometry on device (leaf order for edges)
+    double *d_xyz = nullptr;        // [nv][3]
+    int *d_tri = nullptr;           // [nt][3]
+    double *d_area = nullptr, *d_nrm = nullptr, *d_qpt = nullptr;
+    int *d_etri = nullptr, *d_efree = nullptr;   // [ne][2] leaf order
+    double *d_elen = nullptr;
+    int *d_perm = nullptr;          // leaf -> canonical
+
+    // near-field store (g >= 2), row-major by target (leaf order)
+    int64_t near_pairs = 0, near_nnz = 0;
+    int *d_nrow_ptr = nullptr;      // [ne+1] pair ranges per row
+    int *d_npair_j = nullptr;       // [pairs] source edge (leaf order)
+    int *d_npair_g0 = nullptr;      // [pairs] first stored lag (>= 2)
+    int *d_npair_len = nullptr;     // [pairs]
+    int64_t *d_npair_off = nullptr; // [pairs] value offset
+    double *d_nval = nullptr;       // [nnz] FP64 values
+    float *d_nval32 = nullptr;      // [nnz] FP32 copy (precision forms)
+    int max_lag = 0;
+
+    // Z0 = Zt^(1) CSR (leaf order)
+    int64_t z0_nnz = 0;
+    int *d_z0_ptr = nullptr, *d_z0_col = nullptr;
+    double *d_z0_val = nullptr, *d_z0_dinv = nullptr;
+
+    // march state
+    double *d_Jring = nullptr;      // [ne][ring][nrhs]
+    double *d_rhs = nullptr;        // [ne][nrhs] right-hand side of the step
+    double *d_x = nullptr;          // [ne][nrhs] current solution (leaf order)
+    double *d_work = nullptr;       // GMRES workspace
+    double *d_scal = nullptr;       // small device scalars
+    double *h_scal = nullptr;       // pinned host mirror
+    double *d_pulse = nullptr;      // [nrhs][11]
+    double *d_tmp = nullptr;        // [ne][nrhs] scratch (canonical order io)
+
+    // host copies of the coefficient pair structure (leaf order, sorted by row)
+    std::vector<int> hp_i, hp_j, hp_lo, hp_hi;
+    std::vector<int64_t> hp_off;
+    int64_t hp_nnz = 0;
+
+    // space-time hierarchy (IFMM)
+    std::vector<int> Mt;            // steps per interval per level (0 for levels < 2)
+    int window = 0;                 // source intervals per M2L (mu + 1)
+    int far_ring_need = 0;          // history ring length the far field needs
+    tdbem::FarState *far = nullptr;
+};

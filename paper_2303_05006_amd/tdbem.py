@@ -1,0 +1,201 @@
+"""ctypes binding of libtdbem.so (argument marshalling only).
+
+Every step of the time-domain CFIE path runs in the HIP library; this module
+only converts arguments.  Device buffers are torch tensors on the current HIP
+device; work is issued on torch's current stream unless one is given.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdbem.so")
+_LIB = None
+
+# error codes and enums (mirror include/tdbem.h)
+OK, EINVAL, ENOMEM, EHIP, EBREAKDOWN, ENOCONV, EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
+MODE_DIRECT, MODE_IFMM = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
+GUESS_EXTRAP, GUESS_LEARNED = 0, 1
+Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
+    Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS = range(15)
+
+EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
+           "tdbem_query", "tdbem_near_rows", "tdbem_destroy", "tdbem_last_error"]
+
+
+class TdbemError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"tdbem error {code}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int64), ("xyz", ctypes.c_void_p),
+                ("n_triangles", ctypes.c_int64), ("tri", ctypes.c_void_p)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_double), ("nt", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("mu", ctypes.c_double),
+                ("theta", ctypes.c_double), ("zeta", ctypes.c_double),
+                ("p_s", ctypes.c_int32), ("p_t", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("leaf_max", ctypes.c_int32), ("min_level", ctypes.c_int32), ("mu_window", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
+                ("gmres_rtol", ctypes.c_double), ("gmres_maxit", ctypes.c_int32), ("guess", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+def load():
+    """Load the HIP library; raises if it has not been built (no fallback)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2303_05006_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.tdbem_setup.argtypes = [ctypes.POINTER(_Mesh), ctypes.POINTER(_Config), ctypes.POINTER(P)]
+        L.tdbem_incident_planewave.argtypes = [P, P, i32, P]
+        L.tdbem_potentials.argtypes = [P, P, i32, P]
+        L.tdbem_step.argtypes = [P, P, P]
+        L.tdbem_reset.argtypes = [P]
+        L.tdbem_query.argtypes = [P, i32, P]
+        L.tdbem_near_rows.argtypes = [P, P, i32, i32, P]
+        L.tdbem_destroy.argtypes = [P]
+        L.tdbem_destroy.restype = None
+        L.tdbem_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            L[name].restype = L[name].restype if name in ("tdbem_destroy", "tdbem_last_error") else ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(rc):
+    if rc != OK:
+        raise TdbemError(rc, load().tdbem_last_error().decode())
+
+
+@dataclass
+class Config:
+    dt: float
+    nt: int = 1000
+    eps: float = 8.854187817620389e-12
+    mu: float = 4e-7 * np.pi
+    theta: float = 1.0
+    zeta: float = 299792458.0 / 2
+    p_s: int = 4
+    p_t: int = 4
+    leaf_max: int = 64
+    min_level: int = 2
+    mu_window: int = 8
+    mode: int = MODE_IFMM
+    precision: int = FP64
+    n_rhs: int = 1
+    gmres_rtol: float = 1e-8
+    gmres_maxit: int = 60
+    guess: int = GUESS_EXTRAP
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Solver:
+    """One TDBEM context on the current device."""
+
+    def __init__(self, verts, tris, cfg: Config, stream=None):
+        import torch
+        L = load()
+        self.cfg = cfg
+        self._verts = np.ascontiguousarray(verts, dtype=np.float64)
+        self._tris = np.ascontiguousarray(tris, dtype=np.int32)
+        m = _Mesh(len(self._verts), self._verts.ctypes.data_as(ctypes.c_void_p),
+                  len(self._tris), self._tris.ctypes.data_as(ctypes.c_void_p))
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        c = _Config(cfg.dt, cfg.nt, 2, cfg.eps, cfg.mu, cfg.theta, cfg.zeta, cfg.p_s, cfg.p_t, 0,
+                    cfg.leaf_max, cfg.min_level, cfg.mu_window, cfg.mode, cfg.precision, cfg.n_rhs,
+                    cfg.gmres_rtol, cfg.gmres_maxit, cfg.guess, ctypes.c_void_p(s.cuda_stream))
+        h = ctypes.c_void_p()
+        _check(L.tdbem_setup(ctypes.byref(m), ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+        self.ne = self.query_i64(Q_NE)
+
+    # -------------------------------------------------------------- queries
+    def query_i64(self, key):
+        v = ctypes.c_int64()
+        _check(load().tdbem_query(self._h, key, ctypes.byref(v)))
+        return v.value
+
+    def query_i32(self, key):
+        v = ctypes.c_int32()
+        _check(load().tdbem_query(self._h, key, ctypes.byref(v)))
+        return v.value
+
+    def query_f64(self, key):
+        v = ctypes.c_double()
+        _check(load().tdbem_query(self._h, key, ctypes.byref(v)))
+        return v.value
+
+    def query_array(self, key, n, dtype):
+        a = np.zeros(n, dtype=dtype)
+        _check(load().tdbem_query(self._h, key, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def edges(self):
+        return self.query_array(Q_EDGES, 2 * self.ne, np.int32).reshape(-1, 2)
+
+    def lmax(self):
+        return self.query_i32(Q_LMAX)
+
+    def info(self):
+        lm = self.lmax()
+        return {"ne": self.ne, "lmax": lm, "Mt": self.query_array(Q_MT, lm + 1, np.int32).tolist(),
+                "ncells": self.query_array(Q_NCELLS, lm + 1, np.int32).tolist(),
+                "nilist": self.query_array(Q_NILIST, lm + 1, np.int64).tolist(),
+                "near_nnz": self.query_i64(Q_NEAR_NNZ), "near_pairs": self.query_i64(Q_NEAR_PAIRS),
+                "z0_nnz": self.query_i64(Q_Z0_NNZ), "window": self.query_i32(Q_WINDOW),
+                "device_bytes": self.query_i64(Q_DEVICE_BYTES), "setup_ms": self.query_f64(Q_SETUP_MS)}
+
+    # ----------------------------------------------------------------- work
+    def incident(self, pulses, step, V):
+        pa = np.ascontiguousarray(np.stack([p.as_array() if hasattr(p, "as_array") else np.asarray(p, float)
+                                            for p in pulses]), dtype=np.float64)
+        _check(load().tdbem_incident_planewave(self._h, pa.ctypes.data_as(ctypes.c_void_p), int(step), _ptr(V)))
+
+    def step(self, V, J):
+        _check(load().tdbem_step(self._h, _ptr(V), _ptr(J)))
+
+    def step_rc(self, V, J):
+        return load().tdbem_step(self._h, _ptr(V), _ptr(J))
+
+    def potentials(self, hist, n_hist, out):
+        _check(load().tdbem_potentials(self._h, _ptr(hist) if n_hist > 0 else None, int(n_hist), _ptr(out)))
+
+    def reset(self):
+        _check(load().tdbem_reset(self._h))
+
+    def near_rows(self, rows, G):
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        out = np.zeros((len(rows), self.ne, G))
+        _check(load().tdbem_near_rows(self._h, rows.ctypes.data_as(ctypes.c_void_p), len(rows), int(G),
+                                      out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def gmres_iters(self):
+        return self.query_i32(Q_GMRES_ITERS)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().tdbem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

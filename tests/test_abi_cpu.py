@@ -1,0 +1,41 @@
+"""The C-ABI library loads and exports every function include/tdbem.h declares
+(no compute calls: no GPU is needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2303_05006_amd import tdbem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tdbem.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tdbem_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_path_calls():
+    names = declared_functions()
+    for n in ("tdbem_setup", "tdbem_potentials", "tdbem_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(tdbem.LIB_PATH):
+        pytest.fail("libtdbem.so is not built (run paper_2303_05006_amd/build.py)")
+    lib = ctypes.CDLL(tdbem.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(tdbem.EXPORTS) == set(declared_functions())
+
+
+def test_config_struct_layout_matches_header():
+    # field order of tdbem_config in the header equals the binding's
+    src = open(os.path.join(ROOT, "include", "tdbem.h")).read()
+    body = src[src.index("typedef struct {\n    double dt;"):src.index("} tdbem_config;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"[\s,]\*?([a-z_0-9]+)\s*[,;]", body)
+    assert names == [f[0] for f in tdbem._Config._fields_]

@@ -166,6 +166,26 @@ def test_lag_sums_equal_static_integrals(x, self_term):
     assert np.allclose(tot[6:9], ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
 
 
+def _above(l1, l2, l3, h):
+    P = _tri()
+    n = np.cross(P[1] - P[0], P[2] - P[0]); n /= np.linalg.norm(n)
+    return l1 * P[0] + l2 * P[1] + l3 * P[2] + h * n
+
+
+@pytest.mark.parametrize("x", [
+    _above(0.6, 0.4, 0.0, 0.3),      # projection on an edge (subtended angle pi)
+    _above(1.3, -0.3, 0.0, -0.2),    # projection on an edge's extension
+    _above(1.0, 0.0, 0.0, 0.25),     # projection on a vertex (corner angle)
+    _above(0.5, 0.5, 0.0, 0.02),     # close above the edge midpoint
+])
+def test_lag_sums_static_projection_on_boundary(x):
+    P = _tri()
+    tot, _ = _sum_over_lags(x, P, False)
+    s_pot, g_pot = static_potentials(x, P)
+    assert abs(tot[1] - s_pot) < 1e-12 * s_pot
+    assert np.allclose(tot[6:9], ZETA * g_pot, rtol=1e-11, atol=1e-11 * np.abs(ZETA * g_pot).max())
+
+
 def test_full_disk_and_annulus_closed_forms():
     """Field point above the interior with every light-cone circle inside the
     triangle: each lag integral is 2 pi int_{|h|}^{inf} phi(r) r dr in closed form."""
@@ -275,10 +295,12 @@ def test_per_lag_vectors_against_subdivision_brute_force(x):
 
 
 # ------------------------------------------------------------ assembled matrix
-def test_lag_sum_of_coefficients_is_static_operator():
+@pytest.mark.parametrize("mesh", ["ico1", "cube2"])
+def test_lag_sum_of_coefficients_is_static_operator(mesh):
     """sum_g Zt^(g)_ij = phi-part with 1/r + theta eta zeta (static n x grad part
-    + 1/2 Gram): each piece written from the static closed forms."""
-    m = O.Mesh(*icosphere(1))
+    + 1/2 Gram): each piece written from the static closed forms.  The cube has
+    coplanar neighbours and projections landing on edge lines."""
+    m = O.Mesh(*(icosphere(1) if mesh == "ico1" else cube(2, 2.0)))
     cdt = 0.12
     theta, zeta = 1.0, C0 / 2
     rows = [0, 17, 55]
