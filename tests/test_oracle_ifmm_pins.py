@@ -1,0 +1,156 @@
+"""Pins of the plain IFMM oracle (O2).
+
+* Table 1 of Section 4.1: maximum level and steps per interval of the
+  space-time hierarchy for the paper's sphere meshes.
+* Program 2 / the interaction lists: near pairs and far pairs (through I(C) at
+  exactly one level) cover every (target, source) pair exactly once.
+* Polynomial-kernel exactness: with kernels of degree <= 3 in every variable the
+  Lagrange interpolation of Eq. U_expand is exact, so the whole chain
+  P2M -> M2M -> M2L -> L2L -> L2P must equal a direct double quadrature over
+  the same far pairs and earlier source intervals (written here from the
+  channel definitions of Eqs. ddotA_M, dotphi_fmm, P_fmm and eval).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle.ifmm import IFMM, Hierarchy, W_KAPPA
+from paper_2303_05006_amd.inputs import icosphere, C0, EPS0, MU0
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(HERE, "golden", "table1_hierarchy.json")))["cases"])
+def test_table1_hierarchy(case):
+    v, f = icosphere(case["levels"], 0.5)
+    assert len(f) == case["n_triangles"]
+    m = O.Mesh(v, f)
+    H = Hierarchy(m, 0.005, leaf_max=99)
+    assert H.lmax == case["lmax"]
+    assert H.Mt[H.lmax] == case["Mt"]
+
+
+def _far_level(H, leaf, i, j):
+    """Level at which the ancestors of i and j are in each other's interaction
+    list, or None for a near pair."""
+    li, ci = leaf[i]
+    lj, cj = leaf[j]
+    anc_i = {li: ci}
+    for l in range(li, 0, -1):
+        anc_i[l - 1] = H.levels[l][anc_i[l]].parent
+    anc_j = {lj: cj}
+    for l in range(lj, 0, -1):
+        anc_j[l - 1] = H.levels[l][anc_j[l]].parent
+    for l in range(2, min(li, lj) + 1):
+        if anc_j[l] in H.ilist[l][anc_i[l]]:
+            return l
+    return None
+
+
+def test_near_far_partition_covers_all_pairs_once():
+    v, f = icosphere(2)
+    m = O.Mesh(v, f)
+    H = Hierarchy(m, 0.05, leaf_max=6)
+    assert H.lmax >= 3
+    leaf = H.leaf_of_edge()
+    near = H.near_pairs()
+    assert len(near) == len(set(near))
+    near = set(near)
+    for i in range(m.ne):
+        for j in range(m.ne):
+            fl = _far_level(H, leaf, i, j)
+            assert (fl is None) == ((i, j) in near), (i, j)
+    # lists: neighbours symmetric, interaction lists never touch
+    for l in range(2, H.lmax + 1):
+        for c in range(len(H.levels[l])):
+            for s in H.nbr[l][c]:
+                assert c in H.nbr[l][s]
+            for s in H.ilist[l][c]:
+                d = max(abs(a - b) for a, b in zip(H.levels[l][s].idx, H.levels[l][c].idx))
+                assert 2 <= d <= 3
+
+
+# polynomial kernels in (r^2, tau): degree 2 in every coordinate, 2 in time
+P0 = (0.3, -0.7, 1.1, 0.45, 0.2)
+P1 = (-0.4, 0.25, 0.6, -0.3, 0.5)
+
+
+def _poly(cf):
+    a0, a1, a2, a3, a4 = cf
+
+    def k(r, tau):
+        r2 = r * r
+        return a0 + a1 * r2 + a2 * tau + a3 * tau * tau + a4 * r2 * tau
+    return k
+
+
+def test_polynomial_kernel_exactness():
+    v, f = icosphere(2)
+    m = O.Mesh(v, f)
+    dt = 0.03 / C0
+    theta, zeta = 1.0, C0 / 2
+    F = IFMM(m, dt, theta, zeta, EPS0, MU0, leaf_max=6, kernels=(_poly(P1), _poly(P0)))
+    H = F.H
+    assert H.lmax >= 3 and H.Mt[H.lmax] >= 3
+    nb = 4 * H.Mt[2] + 3
+    rng = np.random.default_rng(5)
+    J = rng.standard_normal((nb, m.ne))
+    far = F.far_history(J)
+    # direct double quadrature
+    Jh = np.zeros_like(J)
+    for b in range(nb):
+        for k in range(4):
+            if b - k >= 0:
+                Jh[b] += W_KAPPA[k] * J[b - k]
+    leaf = H.leaf_of_edge()
+    eta = math.sqrt(MU0 / EPS0)
+    sc = (C0 * dt) ** -2
+    a0, a1, a2, a3, a4 = P0
+    b0, b1, b2, b3, b4 = P1
+    targets = list(range(0, m.ne, 29))
+    ref = np.zeros((nb + 1, len(targets)))
+    avec = np.arange(1, nb + 2)
+    bvec = np.arange(nb)
+    TAU = (avec[:, None] - bvec[None, :]) * dt                  # [a, beta]
+    for ti, i in enumerate(targets):
+        # test side: points, weights, f_i, div f_i, inward normal
+        Xi = []
+        for rho in (0, 1):
+            t_ = m.etri[i, rho]
+            X, W = m.quad_points(t_)
+            for x, w in zip(X, W):
+                fi, divi = m.rwg(i, rho, x)
+                Xi.append((x, w, fi, divi, -m.n_out[t_]))
+        for j in range(m.ne):
+            l = _far_level(H, leaf, i, j)
+            if l is None:
+                continue
+            M = H.Mt[l]
+            # quadrature moments of the pair: the kernels are polynomials in (r^2, tau)
+            Sff = Sffr = Sdd = Sddr = SP = 0.0
+            for sg in (0, 1):
+                Xj, Wj = m.quad_points(m.etri[j, sg])
+                for y, wy in zip(Xj, Wj):
+                    fj, divj = m.rwg(j, sg, y)
+                    for x, wx, fi, divi, n_in in Xi:
+                        ww = wx * wy
+                        r2 = float((x - y) @ (x - y))
+                        Sff += ww * (fi @ fj); Sffr += ww * (fi @ fj) * r2
+                        Sdd += ww * divi * divj; Sddr += ww * divi * divj * r2
+                        # theta eta f_i.(n x ((1/4pi) f_j x (y - x))), times the radial factor below
+                        SP += ww * theta * eta / (4 * math.pi) * (fi @ np.cross(n_in, np.cross(fj, y - x)))
+            # vector potential: (mu/4pi) f_i.f_j d/dt[dU-kernel]; scalar: -div_i (-1/4 pi eps) div_j U-kernel;
+            # magnetic: grad_y (d/dt + zeta) K0 = (2 a4 + zeta (2 a1 + 2 a4 tau)) (y - x)
+            T = TAU
+            tot = sc * (MU0 / (4 * math.pi) * ((b2 + 2 * b3 * T) * Sff + b4 * Sffr)
+                        + 1.0 / (4 * math.pi * EPS0) * ((a0 + a2 * T + a3 * T * T) * Sdd + (a1 + a4 * T) * Sddr)
+                        + (2 * a4 + zeta * (2 * a1 + 2 * a4 * T)) * SP)
+            mask = bvec[None, :] < ((avec[:, None] - 1) // M) * M            # earlier intervals at level l
+            ref[:, ti] += (tot * mask) @ Jh[:, j]
+    got = far[:, targets]
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err < 1e-11, err
