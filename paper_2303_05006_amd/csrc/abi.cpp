@@ -62,24 +62,30 @@ static void build_near_pairs(tdbem_ctx *C, std::vector<int> &pi, std::vector<int
         return;
     }
     const Tree &T = C->T;
+    // leaves partition the leaf-ordered edges into contiguous ranges; visiting
+    // them by first edge emits rows in ascending order (the CSR builders need it)
+    std::vector<std::pair<int, std::pair<int, int>>> leaves;
+    for (int l = 0; l <= T.lmax; ++l)
+        for (int c = 0; c < T.lev[l].n; ++c)
+            if (T.lev[l].leaf[c]) leaves.push_back({T.lev[l].ebeg[c], {l, c}});
+    std::sort(leaves.begin(), leaves.end());
     std::vector<std::pair<int, int>> cells;
     std::vector<int> src;
-    for (int l = 0; l <= T.lmax; ++l) {
+    for (auto &lf : leaves) {
+        int l = lf.second.first, c = lf.second.second;
         const Level &L = T.lev[l];
-        for (int c = 0; c < L.n; ++c) {
-            if (!L.leaf[c]) continue;
-            near_source_cells(T, l, c, cells);
-            src.clear();
-            for (auto &sc : cells) {
-                const Level &S = T.lev[sc.first];
-                for (int e = S.ebeg[sc.second]; e < S.eend[sc.second]; ++e) src.push_back(e);
-            }
-            std::sort(src.begin(), src.end());
-            for (int i = L.ebeg[c]; i < L.eend[c]; ++i)
-                for (int j : src) { pi.push_back(i); pj.push_back(j); }
+        near_source_cells(T, l, c, cells);
+        src.clear();
+        for (auto &sc : cells) {
+            const Level &S = T.lev[sc.first];
+            for (int e = S.ebeg[sc.second]; e < S.eend[sc.second]; ++e) src.push_back(e);
         }
+        std::sort(src.begin(), src.end());
+        for (int i = L.ebeg[c]; i < L.eend[c]; ++i)
+            for (int j : src) { pi.push_back(i); pj.push_back(j); }
     }
-    // rows are grouped by leaf cells in Morton order, i.e. already sorted by i
+    for (size_t q = 1; q < pi.size(); ++q)
+        TD_REQUIRE(pi[q] >= pi[q - 1], TDBEM_EINVAL, "internal: near pairs not sorted by row");
 }
 
 static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ctx *C) {

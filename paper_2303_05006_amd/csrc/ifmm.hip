@@ -1,11 +1,518 @@
-// Space-time interpolation-based FMM (placeholder until the far field lands).
+// Space-time interpolation-based FMM for the far field (Section 3).
+//
+// Hierarchy (Section 3.4.1): cells per level, interaction lists I(C), steps per
+// interval M_t(l_max) = floor(d_s/(c dt)), M_t(l) = 2 M_t(l+1).  Interpolation:
+// Lagrange on p equispaced nodes per axis and in time (p_s = p_t = 4, a
+// 256-vector per channel, index ((b1 p + b2) p + b3) p + n as in Section 3.6.1).
+// Channels: 0-2 vector potential (kernel dU/dt = 2c(c(t-s)-r)_+/r), 3 scalar
+// potential and 4-6 magnetic potential (kernel U = (c(t-s)-r)_+^2/r).
+//
+// Time gating (Programs 3-4): when alpha is a multiple of M_t(l), interval k =
+// alpha/M_t - 1 of level l is complete: P2M at leaves, M2M above (upward), then
+// M2L for the next interval k+1, L2L to the children's next two intervals and
+// L2P into the right-hand sides of the steps of interval k+1 (downward).
+//
+// Finite M2L window: sources are the W = mu + 1 most recent intervals.  When
+// every node pair of lag W lies inside the light cone (mu rho >= 4 sqrt 3, rho =
+// c M_t dt / d_s), the node values of U and dU/dt are polynomials of degree <= 2
+// in s there and in every older interval; the interpolant reproduces them, and
+// since the B-spline weights w annihilate quadratics, the whole older history
+// reduces to the oldest window interval's moments built from the current
+// difference truncated at that interval's start (Eq. hat_J with beta* the
+// interval start).  This reproduces the sum over all earlier intervals.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
 #include "ifmm.h"
 
 namespace tdbem {
-void ifmm_setup(tdbem_ctx *) { throw Error{TDBEM_EINVAL, "IFMM mode is not built yet"}; }
-void ifmm_reset(tdbem_ctx *) {}
-void ifmm_destroy(tdbem_ctx *) {}
-void ifmm_subtract_far(tdbem_ctx *, int, double *, hipStream_t) {}
-void ifmm_add_far(tdbem_ctx *, int, double *, hipStream_t) {}
-void ifmm_after_solve(tdbem_ctx *, int, hipStream_t) {}
+
+static constexpr int P = 4;        // interpolation points per axis and in time
+static constexpr int NS = P * P * P;
+static constexpr int NN = NS * P;   // 256
+static constexpr int NCH = 7;
+
+struct FarLevel {
+    int n = 0, M = 0;
+    double ds = 0, hs = 0, ht = 0;
+    int *il_off = nullptr, *il_src = nullptr, *il_code = nullptr;  // interaction lists
+    int *ix = nullptr;                                             // [n][3] integer coords
+    int *ebeg = nullptr, *eend = nullptr;
+    int nleaf = 0, nparent = 0;
+    int *leaf_cells = nullptr, *parent_cells = nullptr;
+    int *child_beg = nullptr, *child_end = nullptr;                // children at level+1
+    double *MM = nullptr;     // [n][WR][2][NCH][nrhs][NN]
+    double *LC = nullptr;     // [n][NCH][nrhs][NN]
+    double *PEND = nullptr;   // [n][2][NCH][nrhs][NN]
+    double *tw = nullptr;     // [M][2][P]: l_m and dl_m/dt at target step q = 1..M
+    double *ls = nullptr;     // [M][P]: l_n at source step beta - kM = 0..M-1
+};
+
+struct FarState {
+    int lmax = 0, W = 0, WR = 0, FR = 0, nrhs = 1;
+    std::vector<FarLevel> lev;
+    double *Wm = nullptr;     // [ne][NCH][NS] P2M weights
+    double *El = nullptr;     // [ne][NCH][NS] L2P weights
+    double *FAR = nullptr;    // [FR][ne][nrhs] far-field potential per target slot
+    double *S1 = nullptr;     // [2][P][P]: parent cardinal at child node, half h
+};
+
+// ------------------------------------------------------------ host helpers
+static void lagr(double xi, double *v, double *d) {
+    double w[P];
+    for (int n = 0; n < P; ++n) w[n] = -1.0 + 2.0 * n / (P - 1);
+    for (int n = 0; n < P; ++n) {
+        double den = 1.0, prod = 1.0, der = 0.0;
+        for (int m = 0; m < P; ++m) {
+            if (m == n) continue;
+            den *= w[n] - w[m];
+            prod *= xi - w[m];
+        }
+        for (int k = 0; k < P; ++k) {
+            if (k == n) continue;
+            double t = 1.0;
+            for (int m = 0; m < P; ++m)
+                if (m != n && m != k) t *= xi - w[m];
+            der += t;
+        }
+        v[n] = prod / den;
+        if (d) d[n] = der / den;
+    }
+}
+
+template <typename T>
+static T *falloc(tdbem_ctx *C, size_t n) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess)
+        throw Error{TDBEM_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed (far field)"};
+    C->allocs.push_back(p);
+    C->dev_bytes += n * sizeof(T);
+    return (T *)p;
+}
+template <typename T>
+static T *fup(tdbem_ctx *C, const std::vector<T> &v) {
+    T *p = falloc<T>(C, v.size());
+    if (!v.empty()) TD_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+}
+
+void ifmm_setup(tdbem_ctx *C) {
+    const Tree &T = C->T;
+    const HostMesh &H = C->H;
+    TD_REQUIRE(C->cfg.p_s == P && C->cfg.p_t == P, TDBEM_EINVAL, "the far field is built for p_s = p_t = 4");
+    TD_REQUIRE(T.lmax >= 2, TDBEM_EINVAL, "IFMM needs at least two levels below the root");
+    FarState *F = new FarState();
+    C->far = F;
+    F->lmax = T.lmax;
+    F->nrhs = C->nrhs;
+    const double ds_max = T.side / std::ldexp(1.0, T.lmax);
+    int Mmax = (int)std::floor(ds_max / C->cdt);
+    TD_REQUIRE(Mmax >= 3, TDBEM_EBREAKDOWN,
+               "time hierarchy breaks down: floor(d_s/(c dt)) = " + std::to_string(Mmax) + " < 3 steps per finest interval");
+    double rho = C->cdt * Mmax / ds_max;
+    int mu = std::max(C->cfg.mu_window, (int)std::ceil(4.0 * std::sqrt(3.0) / rho - 1e-12));
+    F->W = mu + 1;
+    F->WR = F->W + 1;
+    C->window = F->W;
+    C->Mt.assign(T.lmax + 1, 0);
+    F->lev.resize(T.lmax + 1);
+    for (int l = 2; l <= T.lmax; ++l) C->Mt[l] = Mmax << (T.lmax - l);
+    int FR = 8;
+    while (FR < 2 * C->Mt[2] + 2) FR <<= 1;
+    F->FR = FR;
+    C->far_ring_need = C->Mt[2] + 4;
+    const int nr = C->nrhs;
+    // per-level structure
+    for (int l = 2; l <= T.lmax; ++l) {
+        const Level &L = T.lev[l];
+        FarLevel &FL = F->lev[l];
+        FL.n = L.n;
+        FL.M = C->Mt[l];
+        FL.ds = T.side / std::ldexp(1.0, l);
+        FL.hs = 0.5 * FL.ds;
+        FL.ht = 0.5 * FL.M * C->cfg.dt;
+        FL.il_off = fup(C, L.il_off);
+        FL.il_src = fup(C, L.il_src);
+        FL.il_code = fup(C, L.il_code);
+        std::vector<int> ix(3 * (size_t)L.n);
+        for (int c = 0; c < L.n; ++c) { ix[3 * c] = L.ix[c]; ix[3 * c + 1] = L.iy[c]; ix[3 * c + 2] = L.iz[c]; }
+        FL.ix = fup(C, ix);
+        FL.ebeg = fup(C, L.ebeg);
+        FL.eend = fup(C, L.eend);
+        std::vector<int> lc, pc;
+        for (int c = 0; c < L.n; ++c) (L.leaf[c] ? lc : pc).push_back(c);
+        FL.nleaf = (int)lc.size();
+        FL.nparent = (int)pc.size();
+        FL.leaf_cells = fup(C, lc);
+        FL.parent_cells = fup(C, pc);
+        FL.child_beg = fup(C, L.child_beg);
+        FL.child_end = fup(C, L.child_end);
+        FL.MM = falloc<double>(C, (size_t)L.n * F->WR * 2 * NCH * nr * NN);
+        FL.LC = falloc<double>(C, (size_t)L.n * NCH * nr * NN);
+        FL.PEND = falloc<double>(C, (size_t)L.n * 2 * NCH * nr * NN);
+        // time tables: targets t = (k+1) d_t + q dt, q = 1..M, in the target interval
+        // [(k+1) d_t, (k+2) d_t]: xi = 2q/M - 1; sources beta - kM = 0..M-1: xi = 2(beta-kM)/M - 1
+        std::vector<double> tw((size_t)FL.M * 2 * P), ls((size_t)FL.M * P);
+        for (int q = 1; q <= FL.M; ++q) {
+            double v[P], d[P];
+            lagr(2.0 * q / FL.M - 1.0, v, d);
+            for (int m = 0; m < P; ++m) {
+                tw[((size_t)(q - 1) * 2 + 0) * P + m] = v[m];
+                tw[((size_t)(q - 1) * 2 + 1) * P + m] = d[m] / FL.ht;
+            }
+        }
+        for (int b = 0; b < FL.M; ++b) {
+            double v[P];
+            lagr(2.0 * b / FL.M - 1.0, v, nullptr);
+            for (int n = 0; n < P; ++n) ls[(size_t)b * P + n] = v[n];
+        }
+        FL.tw = fup(C, tw);
+        FL.ls = fup(C, ls);
+    }
+    // per-edge P2M / L2P weights at the interior 3-point rule of both triangles
+    const int ne = C->ne;
+    std::vector<double> Wm((size_t)ne * NCH * NS, 0.0), El((size_t)ne * NCH * NS, 0.0);
+    const double PI4 = 4.0 * M_PI;
+    const double sc = 1.0 / (C->cdt * C->cdt);   // (c dt)^{-d}, d = 2
+    for (int p = 0; p < ne; ++p) {
+        int e = T.perm[p];
+        int l = T.edge_leaf_level[p], cell = T.edge_leaf_cell[p];
+        const Level &L = T.lev[l];
+        double ds = T.side / std::ldexp(1.0, l), hs = 0.5 * ds;
+        double cen[3] = {T.origin[0] + (L.ix[cell] + 0.5) * ds, T.origin[1] + (L.iy[cell] + 0.5) * ds,
+                         T.origin[2] + (L.iz[cell] + 0.5) * ds};
+        for (int sd = 0; sd < 2; ++sd) {
+            int t = H.etri[2 * e + sd];
+            double A = H.area[t];
+            double s = (sd == 0 ? 1.0 : -1.0) * H.elen[e] / (2.0 * A);
+            double div = 2.0 * s;
+            const double *o = &H.xyz[3 * H.efree[2 * e + sd]];
+            double nin[3] = {-H.nrm[3 * t], -H.nrm[3 * t + 1], -H.nrm[3 * t + 2]};
+            for (int q = 0; q < 3; ++q) {
+                const double *x = &H.qpt[9 * t + 3 * q];
+                double w = A / 3.0;
+                double f[3] = {s * (x[0] - o[0]), s * (x[1] - o[1]), s * (x[2] - o[2])};
+                double fxn[3] = {f[1] * nin[2] - f[2] * nin[1], f[2] * nin[0] - f[0] * nin[2], f[0] * nin[1] - f[1] * nin[0]};
+                double v[3][P], d[3][P];
+                for (int k = 0; k < 3; ++k) lagr((x[k] - cen[k]) / hs, v[k], d[k]);
+                for (int b1 = 0; b1 < P; ++b1)
+                    for (int b2 = 0; b2 < P; ++b2)
+                        for (int b3 = 0; b3 < P; ++b3) {
+                            int b = (b1 * P + b2) * P + b3;
+                            double lb = v[0][b1] * v[1][b2] * v[2][b3];
+                            double gb[3] = {d[0][b1] * v[1][b2] * v[2][b3] / hs, v[0][b1] * d[1][b2] * v[2][b3] / hs,
+                                            v[0][b1] * v[1][b2] * d[2][b3] / hs};
+                            double fxg[3] = {f[1] * gb[2] - f[2] * gb[1], f[2] * gb[0] - f[0] * gb[2], f[0] * gb[1] - f[1] * gb[0]};
+                            double *wm = &Wm[(size_t)p * NCH * NS];
+                            double *el = &El[(size_t)p * NCH * NS];
+                            for (int c = 0; c < 3; ++c) {
+                                wm[c * NS + b] += w * sc * C->cfg.mu / PI4 * f[c] * lb;
+                                wm[(4 + c) * NS + b] += w * sc / PI4 * fxg[c];
+                                el[c * NS + b] += w * f[c] * lb;
+                                el[(4 + c) * NS + b] += w * C->cfg.theta * C->eta * fxn[c] * lb;
+                            }
+                            wm[3 * NS + b] += w * sc * (-1.0 / (PI4 * C->cfg.eps)) * div * lb;
+                            el[3 * NS + b] += w * (-div) * lb;
+                        }
+            }
+        }
+    }
+    F->Wm = fup(C, Wm);
+    F->El = fup(C, El);
+    std::vector<double> S1(2 * P * P);
+    for (int h = 0; h < 2; ++h)
+        for (int bc = 0; bc < P; ++bc) {
+            double v[P];
+            lagr((h - 0.5) + 0.5 * (-1.0 + 2.0 * bc / (P - 1)), v, nullptr);
+            for (int bp = 0; bp < P; ++bp) S1[(h * P + bp) * P + bc] = v[bp];   // [h][parent][child]
+        }
+    F->S1 = fup(C, S1);
+    F->FAR = falloc<double>(C, (size_t)F->FR * ne * nr);
+    ifmm_reset(C);
+}
+
+void ifmm_reset(tdbem_ctx *C) {
+    FarState *F = C->far;
+    if (!F) return;
+    hipStream_t s = C->stream;
+    const int nr = C->nrhs;
+    for (int l = 2; l <= F->lmax; ++l) {
+        FarLevel &FL = F->lev[l];
+        TD_HIP(hipMemsetAsync(FL.MM, 0, sizeof(double) * (size_t)FL.n * F->WR * 2 * NCH * nr * NN, s));
+        TD_HIP(hipMemsetAsync(FL.PEND, 0, sizeof(double) * (size_t)FL.n * 2 * NCH * nr * NN, s));
+        TD_HIP(hipMemsetAsync(FL.LC, 0, sizeof(double) * (size_t)FL.n * NCH * nr * NN, s));
+    }
+    TD_HIP(hipMemsetAsync(F->FAR, 0, sizeof(double) * (size_t)F->FR * C->ne * nr, s));
+}
+
+void ifmm_destroy(tdbem_ctx *C) {
+    delete C->far;
+    C->far = nullptr;
+}
+
+// ------------------------------------------------------------------ kernels
+__constant__ double c_wk[4] = {0.5, -1.5, 1.5, -0.5};
+
+// P2M at the leaves of one level: one block per (leaf, rhs).
+// T[j][tf][n] = sum_beta l_n(xi_beta) Jhat^beta_j (tf 0 full, 1 truncated at kM),
+// MM[c][b][n][tf] = sum_j Wm[j][c][b] T[j][tf][n].
+__global__ void __launch_bounds__(256) k_p2m(const int *leaf_cells, const int *ebeg, const int *eend, int k, int M,
+                                             const double *ls, const double *ring, int R, int nrhs,
+                                             const double *Wm, double *MM, int slot, int WR) {
+    int cell = leaf_cells[blockIdx.x];
+    int r = blockIdx.y;
+    int e0 = ebeg[cell], e1 = eend[cell];
+    __shared__ double T[64][2][P];
+    __shared__ double acc_sh[2 * NCH * NN];
+    for (int q = threadIdx.x; q < 2 * NCH * NN; q += blockDim.x) acc_sh[q] = 0.0;
+    int beta0 = k * M;
+    for (int jb = e0; jb < e1; jb += 64) {
+        int nj = min(64, e1 - jb);
+        __syncthreads();
+        for (int q = threadIdx.x; q < nj * 2 * P; q += blockDim.x) {
+            int j = q / (2 * P), tf = (q / P) % 2, n = q % P;
+            const double *J = ring + (size_t)(jb + j) * R * nrhs + r;
+            double s = 0.0;
+            for (int bo = 0; bo < M; ++bo) {
+                int beta = beta0 + bo;
+                double jh = 0.0;
+                int kmax = tf ? min(3, bo) : 3;
+                for (int kap = 0; kap <= kmax; ++kap) {
+                    int b = beta - kap;
+                    if (b >= 0) jh += c_wk[kap] * J[(size_t)(b & (R - 1)) * nrhs];
+                }
+                s += ls[bo * P + n] * jh;
+            }
+            T[j][tf][n] = s;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < NCH * NS; q += blockDim.x) {
+            int c = q / NS, b = q % NS;
+            double a[2][P] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+            for (int j = 0; j < nj; ++j) {
+                double w = Wm[((size_t)(jb + j) * NCH + c) * NS + b];
+                for (int tf = 0; tf < 2; ++tf)
+                    for (int n = 0; n < P; ++n) a[tf][n] += w * T[j][tf][n];
+            }
+            for (int tf = 0; tf < 2; ++tf)
+                for (int n = 0; n < P; ++n) acc_sh[(tf * NCH + c) * NN + b * P + n] += a[tf][n];
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < 2 * NCH * NN; q += blockDim.x) {
+        int tf = q / (NCH * NN), c = (q / NN) % NCH, v = q % NN;
+        MM[((((size_t)cell * WR + slot) * 2 + tf) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = acc_sh[q];
+    }
+}
+
+// M2M for the non-leaf cells of a level: MM(S, k) = sum_{children, h} T_{oct,h} MM(child, 2k+h);
+// truncated: h = 0 from the child's truncated MM, h = 1 from its full MM.
+// One block per (parent, channel, rhs, tf); thread = output (b, n).
+__global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int *child_beg, const int *child_end,
+                                             const int *cix, const double *S1, const double *MMc, int slot0, int slot1,
+                                             int WRc, double *MMp, int slot, int WRp, int nrhs) {
+    int cell = parent_cells[blockIdx.x];
+    int c = blockIdx.y % NCH, tf = blockIdx.y / NCH;
+    int r = blockIdx.z;
+    int v = threadIdx.x;
+    int b1 = v / (P * P * P), b2 = (v / (P * P)) % P, b3 = (v / P) % P, n = v % P;
+    __shared__ double in[NN];
+    double acc = 0.0;
+    for (int ch = child_beg[cell]; ch < child_end[cell]; ++ch) {
+        int hx = cix[3 * ch] & 1, hy = cix[3 * ch + 1] & 1, hz = cix[3 * ch + 2] & 1;
+        for (int h = 0; h < 2; ++h) {
+            int stf = (tf == 1 && h == 0) ? 1 : 0;
+            int sl = h == 0 ? slot0 : slot1;
+            __syncthreads();
+            in[v] = MMc[((((size_t)ch * WRc + sl) * 2 + stf) * NCH + c) * nrhs * NN + (size_t)r * NN + v];
+            __syncthreads();
+            for (int q = 0; q < NN; ++q) {
+                int q1 = q / (P * P * P), q2 = (q / (P * P)) % P, q3 = (q / P) % P, qn = q % P;
+                double w = S1[(hx * P + b1) * P + q1] * S1[(hy * P + b2) * P + q2] * S1[(hz * P + b3) * P + q3] *
+                           S1[(h * P + n) * P + qn];
+                acc += w * in[q];
+            }
+        }
+    }
+    MMp[((((size_t)cell * WRp + slot) * 2 + tf) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = acc;
+}
+
+// M2L: LC(O) = PEND(O, parity) + sum_{S in I(O)} sum_{m=1}^{W} K(off, m) MM(S, k+1-m),
+// the oldest lag from the truncated moments.  One block per (target, kernel, rhs);
+// thread = output (a, m); node distances of the offset staged in LDS.
+__global__ void __launch_bounds__(256) k_m2l(int n, const int *il_off, const int *il_src, const int *il_code,
+                                             const double *MM, int WR, int k, int W, double hs, double ht, double cl,
+                                             const double *PEND, double *LC, int nrhs) {
+    int O = blockIdx.x;
+    int kind = blockIdx.y;             // 0: channels 0-2 (dU/dt), 1: channels 3-6 (U)
+    int r = blockIdx.z;
+    int v = threadIdx.x;
+    int a = v / P, mt = v % P;
+    int c0 = kind == 0 ? 0 : 3, nc = kind == 0 ? 3 : 4;
+    __shared__ double rab[NS][NS + 1];
+    __shared__ double src[4][NN];
+    double acc[4];
+    int parity = (k + 1) & 1;
+    for (int c = 0; c < nc; ++c)
+        acc[c] = PEND[(((size_t)O * 2 + parity) * NCH + c0 + c) * nrhs * NN + (size_t)r * NN + v];
+    const double dsz = 2.0 * hs;
+    for (int q = il_off[O]; q < il_off[O + 1]; ++q) {
+        int S = il_src[q], code = il_code[q];
+        int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
+        __syncthreads();
+        // distances between target node a and source node b: x_a - y_b = -off ds + hs (w_a - w_b)
+        for (int t = v; t < NS * NS; t += blockDim.x) {
+            int ia = t / NS, ib = t % NS;
+            int i1 = ia / (P * P), i2 = (ia / P) % P, i3 = ia % P;
+            int j1 = ib / (P * P), j2 = (ib / P) % P, j3 = ib % P;
+            double dx = -ox * dsz + hs * (2.0 / (P - 1)) * (i1 - j1);
+            double dy = -oy * dsz + hs * (2.0 / (P - 1)) * (i2 - j2);
+            double dz = -oz * dsz + hs * (2.0 / (P - 1)) * (i3 - j3);
+            rab[ia][ib] = sqrt(dx * dx + dy * dy + dz * dz);
+        }
+        for (int lag = 1; lag <= W; ++lag) {
+            int ks = k + 1 - lag;
+            if (ks < 0) break;
+            int sl = ks % WR, tf = lag == W ? 1 : 0;
+            __syncthreads();
+            for (int c = 0; c < nc; ++c)
+                src[c][v] = MM[((((size_t)S * WR + sl) * 2 + tf) * NCH + c0 + c) * nrhs * NN + (size_t)r * NN + v];
+            __syncthreads();
+            for (int b = 0; b < NS; ++b) {
+                double rr = rab[a][b];
+                for (int nn_ = 0; nn_ < P; ++nn_) {
+                    double tau = lag * 2.0 * ht + ht * (2.0 / (P - 1)) * (mt - nn_);
+                    double u = fmax(cl * tau - rr, 0.0);
+                    double kv = kind == 0 ? 2.0 * cl * u / rr : u * u / rr;
+                    for (int c = 0; c < nc; ++c) acc[c] += kv * src[c][b * P + nn_];
+                }
+            }
+        }
+    }
+    for (int c = 0; c < nc; ++c) LC[((size_t)O * NCH + c0 + c) * nrhs * NN + (size_t)r * NN + v] = acc[c];
+}
+
+// L2L: PEND(child, h) = T_{oct,h}^T LC(parent) for the child's intervals 2(k+1)+h.
+// One block per (parent, channel, rhs, h) per child; thread = child output (a', m').
+__global__ void __launch_bounds__(256) k_l2l(const int *parent_cells, const int *child_beg, const int *child_end,
+                                             const int *cix, const double *S1, const double *LCp, double *PENDc, int nrhs) {
+    int cell = parent_cells[blockIdx.x];
+    int c = blockIdx.y % NCH, h = blockIdx.y / NCH;
+    int r = blockIdx.z;
+    int v = threadIdx.x;
+    int a1 = v / (P * P * P), a2 = (v / (P * P)) % P, a3 = (v / P) % P, m = v % P;
+    __shared__ double in[NN];
+    in[v] = LCp[((size_t)cell * NCH + c) * nrhs * NN + (size_t)r * NN + v];
+    __syncthreads();
+    for (int ch = child_beg[cell]; ch < child_end[cell]; ++ch) {
+        int hx = cix[3 * ch] & 1, hy = cix[3 * ch + 1] & 1, hz = cix[3 * ch + 2] & 1;
+        double acc = 0.0;
+        for (int q = 0; q < NN; ++q) {
+            int q1 = q / (P * P * P), q2 = (q / (P * P)) % P, q3 = (q / P) % P, qn = q % P;
+            double w = S1[(hx * P + q1) * P + a1] * S1[(hy * P + q2) * P + a2] * S1[(hz * P + q3) * P + a3] *
+                       S1[(h * P + qn) * P + m];
+            acc += w * in[q];
+        }
+        PENDc[(((size_t)ch * 2 + h) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = acc;
+    }
+}
+
+// L2P: FAR(slot of step alpha') for the edges of a leaf, alpha' = (k+1)M + q, q = 1..M:
+// sum_c sum_a El[i][c][a] sum_m LC[c][a][m] tw_c(m, q); tw: l_m' for channels 0-2,
+// l_m for 3, l_m' + zeta l_m for 4-6.  One thread per (edge, q, rhs).
+__global__ void k_l2p(const int *leaf_cells, int nleaf, const int *ebeg, const int *eend, int k, int M,
+                      const double *tw, double zeta, const double *El, const double *LC, double *FAR, int FR,
+                      int ne, int nrhs, int maxe) {
+    int lid = blockIdx.x;
+    int cell = leaf_cells[lid];
+    int e0 = ebeg[cell], e1 = eend[cell];
+    int nloc = (e1 - e0) * M * nrhs;
+    for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
+        int j = t / (M * nrhs), q = (t / nrhs) % M + 1, r = t % nrhs;
+        int i = e0 + j;
+        const double *tv = tw + (size_t)(q - 1) * 2 * P;
+        double s = 0.0;
+        for (int c = 0; c < NCH; ++c) {
+            double w[P];
+            for (int m = 0; m < P; ++m) w[m] = c < 3 ? tv[P + m] : (c == 3 ? tv[m] : tv[P + m] + zeta * tv[m]);
+            const double *L = LC + ((size_t)cell * NCH + c) * nrhs * NN + (size_t)r * NN;
+            const double *e = El + ((size_t)i * NCH + c) * NS;
+            for (int a = 0; a < NS; ++a) {
+                double lt = 0.0;
+                for (int m = 0; m < P; ++m) lt += L[a * P + m] * w[m];
+                s += e[a] * lt;
+            }
+        }
+        int alpha = (k + 1) * M + q;
+        FAR[((size_t)((alpha - 1) & (FR - 1)) * ne + i) * nrhs + r] = s;
+    }
+    (void)nleaf; (void)maxe;
+}
+
+__global__ void k_far_apply(int64_t n, double sign, const double *FAR, double *y) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) y[t] += sign * FAR[t];
+}
+
+// ------------------------------------------------------------------ driver
+void ifmm_subtract_far(tdbem_ctx *C, int alpha, double *rhs, hipStream_t s) {
+    FarState *F = C->far;
+    int64_t n = (int64_t)C->ne * C->nrhs;
+    const double *src = F->FAR + (size_t)((alpha - 1) & (F->FR - 1)) * n;
+    hipLaunchKernelGGL(k_far_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, -1.0, src, rhs);
+    TD_HIP(hipGetLastError());
+}
+
+void ifmm_add_far(tdbem_ctx *C, int alpha, double *out, hipStream_t s) {
+    FarState *F = C->far;
+    int64_t n = (int64_t)C->ne * C->nrhs;
+    const double *src = F->FAR + (size_t)((alpha - 1) & (F->FR - 1)) * n;
+    hipLaunchKernelGGL(k_far_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, 1.0, src, out);
+    TD_HIP(hipGetLastError());
+}
+
+void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
+    FarState *F = C->far;
+    const int nr = C->nrhs;
+    // upward pass (Program 3)
+    for (int l = F->lmax; l >= 2; --l) {
+        FarLevel &FL = F->lev[l];
+        if (alpha % FL.M) continue;
+        int k = alpha / FL.M - 1;
+        int slot = k % F->WR;
+        if (FL.nleaf > 0) {
+            hipLaunchKernelGGL(k_p2m, dim3(FL.nleaf, nr), dim3(256), 0, s, FL.leaf_cells, FL.ebeg, FL.eend, k, FL.M,
+                               FL.ls, C->d_Jring, C->ring, nr, F->Wm, FL.MM, slot, F->WR);
+        }
+        if (FL.nparent > 0) {
+            FarLevel &CL = F->lev[l + 1];
+            hipLaunchKernelGGL(k_m2m, dim3(FL.nparent, 2 * NCH, nr), dim3(NN), 0, s, FL.parent_cells, FL.child_beg,
+                               FL.child_end, CL.ix, F->S1, CL.MM, (2 * k) % F->WR, (2 * k + 1) % F->WR, F->WR, FL.MM,
+                               slot, F->WR, nr);
+        }
+        TD_HIP(hipGetLastError());
+    }
+    // downward pass (Program 4)
+    for (int l = 2; l <= F->lmax; ++l) {
+        FarLevel &FL = F->lev[l];
+        if (alpha % FL.M) continue;
+        int k = alpha / FL.M - 1;
+        hipLaunchKernelGGL(k_m2l, dim3(FL.n, 2, nr), dim3(NN), 0, s, FL.n, FL.il_off, FL.il_src, FL.il_code, FL.MM,
+                           F->WR, k, F->W, FL.hs, FL.ht, C->c, FL.PEND, FL.LC, nr);
+        if (FL.nparent > 0) {
+            FarLevel &CL = F->lev[l + 1];
+            hipLaunchKernelGGL(k_l2l, dim3(FL.nparent, 2 * NCH, nr), dim3(NN), 0, s, FL.parent_cells, FL.child_beg,
+                               FL.child_end, CL.ix, F->S1, FL.LC, CL.PEND, nr);
+        }
+        if (FL.nleaf > 0) {
+            hipLaunchKernelGGL(k_l2p, dim3(FL.nleaf), dim3(256), 0, s, FL.leaf_cells, FL.nleaf, FL.ebeg, FL.eend, k,
+                               FL.M, FL.tw, C->cfg.zeta, F->El, FL.LC, F->FAR, F->FR, C->ne, nr, 0);
+        }
+        TD_HIP(hipGetLastError());
+    }
+}
+
 }  // namespace tdbem
