@@ -1,0 +1,200 @@
+"""Benchmark of the marching-on-in-time step of the fast TDBEM on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp64|fp32] [--nrhs R]
+
+A step is one full marching step (incident field read from HBM, near-field
+history sum, far-field passes at the time gates, Z0 solve, history update).
+The workload is the 20480-triangle PEC sphere of radius 1 m (c dt = 0.02 m,
+modulated Gaussian 300/200 MHz, p_s = p_t = 4, leaves of at most 64 edges).
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MOT steps/s and M2L roofline %, chosen vs plain FP64 IFMM at rel err 1e-4"
+PEAK_HBM = 8.0e12          # B/s
+PEAK_FP64 = 78.6e12        # FLOP/s (vector and matrix)
+PEAK_FP32 = 157.3e12
+
+
+def gate_schedule(Mt, lmax, first, last):
+    """Per level, the time gates alpha in [first, last] (alpha % M_t(l) == 0)."""
+    out = {}
+    for l in range(2, lmax + 1):
+        M = Mt[l]
+        out[l] = [a for a in range(first, last + 1) if a % M == 0]
+    return out
+
+
+def cpu_baseline(workload, rows=8):
+    """Oracle (conventional method) history sum per step on a sample of rows."""
+    from oracle import oracle as O
+    from paper_2303_05006_amd.inputs import C0
+    m = O.Mesh(workload.verts, workload.tris)
+    cdt = workload.dt * C0
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(m.ne, rows, replace=False))
+    nthreads = min(16, os.cpu_count() or 1)
+    Z = O.zrows(m, sample, cdt, workload.theta, workload.zeta, nthreads=nthreads)     # untimed: coefficients
+    # sparse lag strips of the sampled rows, as the oracle's history routine takes them
+    r_, c_, g0, ln, off, vals = [], [], [], [], [], []
+    pos = 0
+    for ri in range(rows):
+        nz = np.nonzero(np.abs(Z[ri]).max(axis=1))[0]
+        for j in nz:
+            g = np.nonzero(Z[ri, j])[0]
+            a, b = g.min(), g.max()
+            r_.append(ri); c_.append(j); g0.append(a); ln.append(b - a + 1); off.append(pos)
+            vals.append(Z[ri, j, a:b + 1]); pos += b - a + 1
+    import ctypes
+    L = O.lib()
+    arr = lambda x, t: np.ascontiguousarray(np.array(x, dtype=t))
+    r_, c_, g0, ln = (arr(x, np.int32) for x in (r_, c_, g0, ln))
+    off = arr(off, np.int64)
+    vals = np.ascontiguousarray(np.concatenate(vals))
+    G = Z.shape[2]
+    nb = G + 2
+    hist = rng.standard_normal((nb, m.ne))
+    out = np.zeros(m.ne)
+    P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        L.orc_history(len(r_), P(r_), P(c_), P(g0), P(ln), P(off), P(vals), m.ne, P(hist), nb, nb, 2, P(out))
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > 5.0 and reps >= 3:
+            break
+    per_sample = el / reps
+    per_step = per_sample * m.ne / rows
+    return {"value": 1.0 / per_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"conventional-method history sum sum_g Zt^(g) J^(a-g) over all 30720 source edges and all "
+                       f"lags for {rows} target rows ({pos} stored coefficients; coefficients precomputed, "
+                       f"untimed), {reps} repetitions, scaled by {m.ne}/{rows} rows")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=480)
+    ap.add_argument("--warmup", type=int, default=240)
+    ap.add_argument("--form", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--nrhs", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2303_05006_amd import tdbem
+    from paper_2303_05006_amd.inputs import workload
+
+    torch.cuda.set_device(0)
+    name = "sphere20480" if args.nrhs == 1 else "sphere20480x64"
+    w = workload(name, n_rhs=args.nrhs)
+    nr = len(w.pulses)
+    prec = tdbem.FP64 if args.form == "fp64" else tdbem.FP32
+    cfg = tdbem.Config(dt=w.dt, nt=w.nt, theta=w.theta, zeta=w.zeta, leaf_max=w.leaf_max, mode=tdbem.MODE_IFMM,
+                       precision=prec, n_rhs=nr, gmres_rtol=args.rtol, gmres_maxit=60)
+    t0 = time.perf_counter()
+    S = tdbem.Solver(w.verts, w.tris, cfg)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    info = S.info()
+    ne = S.ne
+    W, K = args.warmup, args.steps
+    last = W + K
+    # incident fields of every step resident in HBM before timing
+    V = torch.zeros((last, nr, ne), dtype=torch.float64, device="cuda")
+    for a in range(1, last + 1):
+        S.incident(w.pulses, a, V[a - 1])
+    J = torch.zeros((nr, ne), dtype=torch.float64, device="cuda")
+    for a in range(1, W + 1):
+        S.step(V[a - 1], J)
+    torch.cuda.synchronize()
+    S.profile(True)
+    iters = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for a in range(W + 1, last + 1):
+        S.step(V[a - 1], J)
+        iters.append(S.gmres_iters())
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    ph = S.phase_times()
+    ms_step = el / K * 1e3
+
+    # algorithmic work in the timed region
+    lmax = info["lmax"]
+    gates = gate_schedule(info["Mt"], lmax, W + 1, last)
+    win = info["window"]
+    m2l_flops = 0.0
+    for l in range(2, lmax + 1):
+        for a in gates[l]:
+            k = a // info["Mt"][l] - 1
+            lags = min(win, k + 1)
+            m2l_flops += info["nilist"][l] * lags * 7 * 2.0 * 256 * 256 * nr
+    vb = 8 if prec == tdbem.FP64 else 4
+    near_bytes = K * (info["near_nnz"] * vb + info["near_pairs"] * 20 + ne * 8 * nr)
+    kernels = {}
+    t_m2l = ph["m2l"][0] * 1e-3
+    t_near = ph["near"][0] * 1e-3
+    if t_m2l > 0:
+        kernels["m2l"] = {"bound": "alu", "achieved": m2l_flops / t_m2l / 1e12, "unit": "TFLOP/s",
+                          "peak": (PEAK_FP64 if prec == tdbem.FP64 else PEAK_FP32) / 1e12,
+                          "launches": ph["m2l"][1], "ms_total": ph["m2l"][0]}
+    if t_near > 0:
+        kernels["near"] = {"bound": "hbm", "achieved": near_bytes / t_near / 1e9, "unit": "GB/s",
+                           "peak": PEAK_HBM / 1e9, "launches": ph["near"][1], "ms_total": ph["near"][0]}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
+    roof = None
+    if dom:
+        kd = kernels[dom]
+        roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
+                "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"], "traffic": None}
+    res = {
+        "metric": METRIC,
+        "value": K / el,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == tdbem.FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{name}: PEC sphere r=1 m, 20480 triangles / {ne} RWG edges, c dt = 0.02 m, "
+                               f"IFMM p_s=p_t=4, leaves <= 64 edges, {nr} incident field(s), steps {W + 1}..{last} of 1000",
+                   "form": args.form, "n_rhs": nr, "gmres_rtol": args.rtol},
+        "roofline": roof,
+        "kernels": kernels,
+        "phase_ms": {k: v[0] for k, v in ph.items()},
+        "gmres_iters_mean": float(np.mean(iters)),
+        "setup_s": setup_s,
+        "hierarchy": {k: info[k] for k in ("lmax", "Mt", "ncells", "nilist", "near_nnz", "near_pairs", "z0_nnz", "window")},
+        "device_gb": info["device_bytes"] / 1e9,
+    }
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(w)
+    S.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -133,7 +133,16 @@ enum {
     TDBEM_Q_DEVICE_BYTES = 11,/* int64: device memory held by the context */
     TDBEM_Q_STEP = 12,       /* int32: next step alpha */
     TDBEM_Q_EDGE_LEAF = 13,  /* int32 [N_e]: internal (leaf-order) position of each canonical edge */
-    TDBEM_Q_SETUP_MS = 14    /* double: wall time of tdbem_setup */
+    TDBEM_Q_SETUP_MS = 14,   /* double: wall time of tdbem_setup */
+    TDBEM_Q_PHASE_MS = 15,   /* double [TDBEM_NPHASE]: device time per phase since profiling was enabled */
+    TDBEM_Q_PHASE_COUNT = 16 /* int64 [TDBEM_NPHASE]: timed launches per phase */
+};
+
+/* Phases timed by tdbem_profile (HIP events on the work stream around each
+ * phase's launches; GMRES time includes its host-side Givens updates). */
+enum {
+    TDBEM_PH_NEAR = 0, TDBEM_PH_GMRES = 1, TDBEM_PH_P2M = 2, TDBEM_PH_M2M = 3, TDBEM_PH_M2L = 4,
+    TDBEM_PH_L2L = 5, TDBEM_PH_L2P = 6, TDBEM_PH_OTHER = 7, TDBEM_NPHASE = 8
 };
 int tdbem_query(const tdbem_ctx *ctx, int32_t key, void *out);
 
@@ -141,6 +150,11 @@ int tdbem_query(const tdbem_ctx *ctx, int32_t key, void *out);
  * ids (host); out host [n][N_e][G] receives Zt^(g)_{row, j}, g = 0..G-1, for
  * every stored near pair (zero elsewhere, g = 1 included). */
 int tdbem_near_rows(tdbem_ctx *ctx, const int32_t *rows, int32_t n, int32_t G, double *out);
+
+/* Enable (1) or disable (0) per-phase timing; enabling clears the counters.
+ * Timing synchronises nothing until a TDBEM_Q_PHASE_* query, which waits for
+ * the stream and folds the recorded event pairs into the totals. */
+int tdbem_profile(tdbem_ctx *ctx, int32_t enable);
 
 void tdbem_destroy(tdbem_ctx *ctx);
 const char *tdbem_last_error(void);

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
@@ -12,6 +13,43 @@ namespace tdbem {
 
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    TD_HIP(hipEventCreate(&e));
+    return e;
+}
+void Profiler::begin(int, hipStream_t s, hipEvent_t &e0) {
+    e0 = get();
+    TD_HIP(hipEventRecord(e0, s));
+}
+void Profiler::end(int ph, hipStream_t s, hipEvent_t e0) {
+    hipEvent_t e1 = get();
+    if (hipEventRecord(e1, s) != hipSuccess) return;
+    pending.push_back({ph, {e0, e1}});
+}
+void Profiler::fold(hipStream_t s) {
+    TD_HIP(hipStreamSynchronize(s));
+    for (auto &p : pending) {
+        float t = 0.f;
+        TD_HIP(hipEventElapsedTime(&t, p.second.first, p.second.second));
+        ms[p.first] += t;
+        count[p.first] += 1;
+        pool.push_back(p.second.first);
+        pool.push_back(p.second.second);
+    }
+    pending.clear();
+}
+void Profiler::clear() {
+    for (auto &p : pending) { pool.push_back(p.second.first); pool.push_back(p.second.second); }
+    pending.clear();
+    for (int i = 0; i < TDBEM_NPHASE; ++i) { ms[i] = 0; count[i] = 0; }
+}
+Profiler::~Profiler() {
+    for (auto &p : pending) { (void)hipEventDestroy(p.second.first); (void)hipEventDestroy(p.second.second); }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
 
 void launch_lag_range(const GeoDev &G, int64_t npairs, const int *pi, const int *pj, int *lo, int *hi, hipStream_t s);
 void launch_zfill(const GeoDev &G, int64_t nnz, int64_t npairs, const int *pi, const int *pj, const int *g0,
@@ -99,6 +137,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->mode == TDBEM_MODE_DIRECT || cfg->mode == TDBEM_MODE_IFMM, TDBEM_EINVAL, "unknown mode");
     TD_REQUIRE(cfg->precision >= TDBEM_FP64 && cfg->precision <= TDBEM_BF16, TDBEM_EINVAL, "unknown precision");
     C->stream = (hipStream_t)cfg->stream;
+    if (const char *dbg = std::getenv("TDBEM_DEBUG_GMRES")) C->debug_gmres = dbg[0] == '1';
     C->nrhs = cfg->n_rhs;
     C->c = 1.0 / std::sqrt(cfg->eps * cfg->mu);
     C->eta = std::sqrt(cfg->mu / cfg->eps);
@@ -240,20 +279,26 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
     int a = C->alpha;
     int rc = TDBEM_OK;
     if (solve) {
-        launch_gather_in(C, V, C->d_rhs, s);
-        launch_near(C, a, C->d_tmp, 1.0, s);
-        launch_axpby(nv, -1.0, C->d_tmp, 1.0, C->d_rhs, s);
-        if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_subtract_far(C, a, C->d_rhs, s);
-        launch_extrap(C, a, C->d_x, s);
+        { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_gather_in(C, V, C->d_rhs, s); }
+        { PhaseScope ps(C->prof, TDBEM_PH_NEAR, s); launch_near(C, a, C->d_tmp, 1.0, s); }
+        {
+            PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
+            launch_axpby(nv, -1.0, C->d_tmp, 1.0, C->d_rhs, s);
+            if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_subtract_far(C, a, C->d_rhs, s);
+            launch_extrap(C, a, C->d_x, s);
+        }
         bool ok = true;
-        C->last_iters = gmres_solve(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, std::max(1, C->cfg.gmres_maxit), &ok, s);
+        {
+            PhaseScope ps(C->prof, TDBEM_PH_GMRES, s);
+            C->last_iters = gmres_solve(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, std::max(1, C->cfg.gmres_maxit), &ok, s);
+        }
         if (!ok) rc = TDBEM_ENOCONV;
     } else {
         launch_gather_in(C, Jgiven, C->d_x, s);
     }
-    launch_ring_put(C, (a - 1) & (C->ring - 1), C->d_x, s);
+    { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_ring_put(C, (a - 1) & (C->ring - 1), C->d_x, s); }
     if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_after_solve(C, a, s);
-    if (Jout) launch_scatter_out(C, C->d_x, Jout, s);
+    if (Jout) { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_scatter_out(C, C->d_x, Jout, s); }
     C->alpha = a + 1;
     return rc;
 }
@@ -358,6 +403,17 @@ int tdbem_query(const tdbem_ctx *C, int32_t key, void *out) {
         case TDBEM_Q_STEP: *(int32_t *)out = C->alpha; break;
         case TDBEM_Q_EDGE_LEAF: std::memcpy(out, T.iperm.data(), sizeof(int) * (size_t)C->ne); break;
         case TDBEM_Q_SETUP_MS: *(double *)out = C->setup_ms; break;
+        case TDBEM_Q_PHASE_MS:
+        case TDBEM_Q_PHASE_COUNT:
+            try {
+                const_cast<tdbem_ctx *>(C)->prof.fold(C->stream);
+            } catch (const Error &e) {
+                set_error(e.msg);
+                return e.code;
+            }
+            if (key == TDBEM_Q_PHASE_MS) std::memcpy(out, C->prof.ms, sizeof(C->prof.ms));
+            else std::memcpy(out, C->prof.count, sizeof(C->prof.count));
+            break;
         default: set_error("unknown query key"); return TDBEM_EINVAL;
     }
     return TDBEM_OK;
@@ -383,6 +439,16 @@ int tdbem_near_rows(tdbem_ctx *C, const int32_t *rows, int32_t n, int32_t G, dou
                     if (g < G) out[((size_t)r * ne + j) * G + g] = val[C->hp_off[p] + (g - C->hp_lo[p])];
             }
         }
+    });
+    return TDBEM_OK;
+}
+
+int tdbem_profile(tdbem_ctx *C, int32_t enable) {
+    if (!C) { set_error("null context"); return TDBEM_EINVAL; }
+    TD_GUARD({
+        C->prof.fold(C->stream);
+        C->prof.clear();
+        C->prof.on = enable != 0;
     });
     return TDBEM_OK;
 }

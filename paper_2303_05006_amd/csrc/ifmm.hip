@@ -33,6 +33,7 @@ static constexpr int P = 4;        // interpolation points per axis and in time
 static constexpr int NS = P * P * P;
 static constexpr int NN = NS * P;   // 256
 static constexpr int NCH = 7;
+static constexpr int M2L_NT = 32;   // columns per M2L tile
 
 struct FarLevel {
     int n = 0, M = 0;
@@ -48,6 +49,11 @@ struct FarLevel {
     double *PEND = nullptr;   // [n][2][NCH][nrhs][NN]
     double *tw = nullptr;     // [M][2][P]: l_m and dl_m/dt at target step q = 1..M
     double *ls = nullptr;     // [M][P]: l_n at source step beta - kM = 0..M-1
+    // offset-major M2L tiles (one right-hand side)
+    int ntile = 0;
+    int *tile_code = nullptr, *tile_kind = nullptr, *tile_col0 = nullptr, *tile_ncol = nullptr;
+    int *col_q = nullptr, *col_ch = nullptr;
+    double *YB = nullptr;     // [interaction-list entries][NCH][NN]
 };
 
 struct FarState {
@@ -114,6 +120,7 @@ void ifmm_setup(tdbem_ctx *C) {
                "time hierarchy breaks down: floor(d_s/(c dt)) = " + std::to_string(Mmax) + " < 3 steps per finest interval");
     double rho = C->cdt * Mmax / ds_max;
     int mu = std::max(C->cfg.mu_window, (int)std::ceil(4.0 * std::sqrt(3.0) / rho - 1e-12));
+    TD_REQUIRE(mu <= 19, TDBEM_EBREAKDOWN, "far-field window of more than 20 intervals (c dt too small for the finest cells)");
     F->W = mu + 1;
     F->WR = F->W + 1;
     C->window = F->W;
@@ -171,6 +178,29 @@ void ifmm_setup(tdbem_ctx *C) {
         }
         FL.tw = fup(C, tw);
         FL.ls = fup(C, ls);
+        if (nr == 1 && !L.il_src.empty()) {
+            // group interaction-list entries by offset; columns (entry, channel) per kernel kind
+            std::vector<std::vector<int>> by(343);
+            for (size_t q = 0; q < L.il_src.size(); ++q) by[L.il_code[q]].push_back((int)q);
+            std::vector<int> tc, tk, t0, tn, cq, cch;
+            for (int code = 0; code < 343; ++code) {
+                if (by[code].empty()) continue;
+                for (int kind = 0; kind < 2; ++kind) {
+                    int c0 = kind == 0 ? 0 : 3, nc = kind == 0 ? 3 : 4;
+                    int start = (int)cq.size();
+                    for (int q : by[code])
+                        for (int c = 0; c < nc; ++c) { cq.push_back(q); cch.push_back(c0 + c); }
+                    for (int b = start; b < (int)cq.size(); b += M2L_NT) {
+                        tc.push_back(code); tk.push_back(kind); t0.push_back(b);
+                        tn.push_back(std::min(M2L_NT, (int)cq.size() - b));
+                    }
+                }
+            }
+            FL.ntile = (int)tc.size();
+            FL.tile_code = fup(C, tc); FL.tile_kind = fup(C, tk); FL.tile_col0 = fup(C, t0); FL.tile_ncol = fup(C, tn);
+            FL.col_q = fup(C, cq); FL.col_ch = fup(C, cch);
+            FL.YB = falloc<double>(C, L.il_src.size() * NCH * NN);
+        }
     }
     // per-edge P2M / L2P weights at the interior 3-point rule of both triangles
     const int ne = C->ne;
@@ -340,59 +370,185 @@ __global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int 
     MMp[((((size_t)cell * WRp + slot) * 2 + tf) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = acc;
 }
 
-// M2L: LC(O) = PEND(O, parity) + sum_{S in I(O)} sum_{m=1}^{W} K(off, m) MM(S, k+1-m),
-// the oldest lag from the truncated moments.  One block per (target, kernel, rhs);
-// thread = output (a, m); node distances of the offset staged in LDS.
-__global__ void __launch_bounds__(256) k_m2l(int n, const int *il_off, const int *il_src, const int *il_code,
-                                             const double *MM, int WR, int k, int W, double hs, double ht, double cl,
-                                             const double *PEND, double *LC, int nrhs) {
-    int O = blockIdx.x;
-    int kind = blockIdx.y;             // 0: channels 0-2 (dU/dt), 1: channels 3-6 (U)
-    int r = blockIdx.z;
-    int v = threadIdx.x;
-    int a = v / P, mt = v % P;
-    int c0 = kind == 0 ? 0 : 3, nc = kind == 0 ? 3 : 4;
-    __shared__ double rab[NS][NS + 1];
-    __shared__ double src[4][NN];
-    double acc[4];
-    int parity = (k + 1) & 1;
-    for (int c = 0; c < nc; ++c)
-        acc[c] = PEND[(((size_t)O * 2 + parity) * NCH + c0 + c) * nrhs * NN + (size_t)r * NN + v];
-    const double dsz = 2.0 * hs;
+// ---------------------------------------------------------------- M2L engine
+// acc[256 x NT] += K(off, lag) X[256 x NT] on the matrix cores.  Rows are target
+// nodes (a, m), columns of X are source moment vectors indexed (b, n); the
+// 16x16x4 instruction's k-step of 4 is one source node b and its 4 time nodes.
+// K is generated per lane: node offsets lie on a lattice of spacing (2/3) h_s in
+// space and (2/3) h_t in time, x_a - y_b = (2/3) h_s ((a - b) - 3 off) and
+// t_m - s_n = (2/3) h_t (3 lag + m - n); distances come from LDS tables indexed
+// by the integer |(a - b) - 3 off|^2 (at most 3 * 12^2 for |off| <= 3).
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+    typedef v4d acc_t;
+    __device__ static acc_t op(double a, double b, acc_t c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int v) { return 4 * v + (lane >> 4); }      // output layout of the f64 form
+};
+template <> struct Mma<float> {
+    typedef v4f acc_t;
+    __device__ static acc_t op(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }      // output layout of the f32 form
+};
+
+static constexpr int QMAX = 433;       // |v|^2 <= 3 * 12^2
+static constexpr int WMAX = 64;        // 3 lag + m - n < 3 W + 3
+
+struct M2LTables {
+    double r[QMAX], ir[QMAX];
+    double ct[WMAX];
+};
+
+__device__ void m2l_tables(M2LTables &tb, double hs, double ht, double cl, int tid) {
+    const double gs = hs * (2.0 / (P - 1)), gt = ht * (2.0 / (P - 1));
+    for (int q = tid; q < QMAX; q += blockDim.x) {
+        double r = gs * sqrt((double)q);
+        tb.r[q] = r;
+        tb.ir[q] = q > 0 ? 1.0 / r : 0.0;
+    }
+    for (int w = tid; w < WMAX; w += blockDim.x) tb.ct[w] = cl * gt * w;
+}
+
+// one operator application: X (LDS, [NN][NT + 1]) for offset (ox, oy, oz) and lag
+template <typename T, int NT>
+__device__ __forceinline__ void m2l_apply(typename Mma<T>::acc_t (&acc)[4][NT / 16], const T (*X)[NT + 1],
+                                          const M2LTables &tb, int ox, int oy, int oz, int lag, int kind, double cl2,
+                                          int wave, int lane) {
+    const int n = lane >> 4;
+    int da[4][3], wv[4];
+    for (int rb = 0; rb < 4; ++rb) {
+        int row = 64 * wave + 16 * rb + (lane & 15);
+        int a = row >> 2, m = row & 3;
+        da[rb][0] = (a >> 4) - 3 * ox;
+        da[rb][1] = ((a >> 2) & 3) - 3 * oy;
+        da[rb][2] = (a & 3) - 3 * oz;
+        wv[rb] = 3 * lag + m - n;
+    }
+    for (int ks = 0; ks < NS; ++ks) {
+        const int b1 = ks >> 4, b2 = (ks >> 2) & 3, b3 = ks & 3;
+        T bv[NT / 16];
+        for (int cb = 0; cb < NT / 16; ++cb) bv[cb] = X[4 * ks + n][16 * cb + (lane & 15)];
+        for (int rb = 0; rb < 4; ++rb) {
+            int d1 = da[rb][0] - b1, d2 = da[rb][1] - b2, d3 = da[rb][2] - b3;
+            int q = d1 * d1 + d2 * d2 + d3 * d3;
+            double u = tb.ct[wv[rb]] - tb.r[q];
+            double kv = u > 0.0 ? (kind == 0 ? cl2 * u * tb.ir[q] : u * u * tb.ir[q]) : 0.0;
+            T av = (T)kv;
+            for (int cb = 0; cb < NT / 16; ++cb) acc[rb][cb] = Mma<T>::op(av, bv[cb], acc[rb][cb]);
+        }
+    }
+}
+
+// offset-major M2L for one right-hand side: one block per (offset, kind, column
+// tile); columns are (interaction-list entry q, channel).  Writes the per-entry
+// contribution YB[q][ch][NN] summed over the window's lags.
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_m2l_off(const int *tile_code, const int *tile_kind, const int *tile_col0,
+                                                 const int *tile_ncol, const int *col_q, const int *col_ch,
+                                                 const int *il_src, const T *MM, int WR, int k, int W, double hs,
+                                                 double ht, double cl, T *YB) {
+    const int tile = blockIdx.x;
+    const int code = tile_code[tile], kind = tile_kind[tile], col0 = tile_col0[tile], ncol = tile_ncol[tile];
+    const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    __shared__ M2LTables tb;
+    __shared__ T X[NN][NT + 1];
+    m2l_tables(tb, hs, ht, cl, tid);
+    typename Mma<T>::acc_t acc[4][NT / 16];
+    for (int rb = 0; rb < 4; ++rb)
+        for (int cb = 0; cb < NT / 16; ++cb) acc[rb][cb] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    for (int lag = 1; lag <= W; ++lag) {
+        int ks = k + 1 - lag;
+        if (ks < 0) break;
+        int sl = ks % WR, tf = lag == W ? 1 : 0;
+        __syncthreads();
+        for (int j = 0; j < NT; ++j) {
+            T v = 0;
+            if (j < ncol) {
+                int q = col_q[col0 + j], ch = col_ch[col0 + j];
+                int S = il_src[q];
+                v = MM[((((size_t)S * WR + sl) * 2 + tf) * NCH + ch) * NN + tid];
+            }
+            X[tid][j] = v;
+        }
+        __syncthreads();
+        m2l_apply<T, NT>(acc, X, tb, ox, oy, oz, lag, kind, 2.0 * cl, wave, lane);
+    }
+    for (int rb = 0; rb < 4; ++rb)
+        for (int cb = 0; cb < NT / 16; ++cb) {
+            int j = 16 * cb + (lane & 15);
+            if (j >= ncol) continue;
+            int q = col_q[col0 + j], ch = col_ch[col0 + j];
+            for (int v = 0; v < 4; ++v) {
+                int row = 64 * wave + 16 * rb + Mma<T>::row(lane, v);
+                YB[((size_t)q * NCH + ch) * NN + row] = acc[rb][cb][v];
+            }
+        }
+}
+
+// LC(O) = PEND(O, parity) + sum over O's interaction-list entries of YB (target-owned, fixed order)
+template <typename T>
+__global__ void k_m2l_reduce(int n, const int *il_off, const T *YB, const T *PEND, int parity, T *LC) {
+    int O = blockIdx.x, c = blockIdx.y, v = threadIdx.x;
+    double s = PEND[(((size_t)O * 2 + parity) * NCH + c) * NN + v];
+    for (int q = il_off[O]; q < il_off[O + 1]; ++q) s += YB[((size_t)q * NCH + c) * NN + v];
+    LC[((size_t)O * NCH + c) * NN + v] = (T)s;
+}
+
+// target-major M2L for batched right-hand sides: one block per (target, kind,
+// (channel, rhs) tile of NT columns); items are (interaction-list source, lag).
+template <typename T, int NT>
+__global__ void __launch_bounds__(256) k_m2l_tgt(const int *il_off, const int *il_src, const int *il_code, const T *MM,
+                                                 int WR, int k, int W, double hs, double ht, double cl, const T *PEND,
+                                                 T *LC, int nrhs) {
+    const int O = blockIdx.x, kind = blockIdx.y;
+    const int c0 = kind == 0 ? 0 : 3, nc = kind == 0 ? 3 : 4;
+    const int ncolt = nc * nrhs;
+    const int col0 = blockIdx.z * NT;
+    if (col0 >= ncolt) return;
+    const int ncol = min(NT, ncolt - col0);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int parity = (k + 1) & 1;
+    __shared__ M2LTables tb;
+    __shared__ T X[NN][NT + 1];
+    m2l_tables(tb, hs, ht, cl, tid);
+    typename Mma<T>::acc_t acc[4][NT / 16];
+    for (int rb = 0; rb < 4; ++rb)
+        for (int cb = 0; cb < NT / 16; ++cb) acc[rb][cb] = typename Mma<T>::acc_t{0, 0, 0, 0};
     for (int q = il_off[O]; q < il_off[O + 1]; ++q) {
         int S = il_src[q], code = il_code[q];
         int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
-        __syncthreads();
-        // distances between target node a and source node b: x_a - y_b = -off ds + hs (w_a - w_b)
-        for (int t = v; t < NS * NS; t += blockDim.x) {
-            int ia = t / NS, ib = t % NS;
-            int i1 = ia / (P * P), i2 = (ia / P) % P, i3 = ia % P;
-            int j1 = ib / (P * P), j2 = (ib / P) % P, j3 = ib % P;
-            double dx = -ox * dsz + hs * (2.0 / (P - 1)) * (i1 - j1);
-            double dy = -oy * dsz + hs * (2.0 / (P - 1)) * (i2 - j2);
-            double dz = -oz * dsz + hs * (2.0 / (P - 1)) * (i3 - j3);
-            rab[ia][ib] = sqrt(dx * dx + dy * dy + dz * dz);
-        }
         for (int lag = 1; lag <= W; ++lag) {
             int ks = k + 1 - lag;
             if (ks < 0) break;
             int sl = ks % WR, tf = lag == W ? 1 : 0;
             __syncthreads();
-            for (int c = 0; c < nc; ++c)
-                src[c][v] = MM[((((size_t)S * WR + sl) * 2 + tf) * NCH + c0 + c) * nrhs * NN + (size_t)r * NN + v];
-            __syncthreads();
-            for (int b = 0; b < NS; ++b) {
-                double rr = rab[a][b];
-                for (int nn_ = 0; nn_ < P; ++nn_) {
-                    double tau = lag * 2.0 * ht + ht * (2.0 / (P - 1)) * (mt - nn_);
-                    double u = fmax(cl * tau - rr, 0.0);
-                    double kv = kind == 0 ? 2.0 * cl * u / rr : u * u / rr;
-                    for (int c = 0; c < nc; ++c) acc[c] += kv * src[c][b * P + nn_];
+            for (int j = 0; j < NT; ++j) {
+                T v = 0;
+                if (j < ncol) {
+                    int cc = (col0 + j) / nrhs, r = (col0 + j) % nrhs;
+                    v = MM[((((size_t)S * WR + sl) * 2 + tf) * NCH + c0 + cc) * nrhs * NN + (size_t)r * NN + tid];
                 }
+                X[tid][j] = v;
             }
+            __syncthreads();
+            m2l_apply<T, NT>(acc, X, tb, ox, oy, oz, lag, kind, 2.0 * cl, wave, lane);
         }
     }
-    for (int c = 0; c < nc; ++c) LC[((size_t)O * NCH + c0 + c) * nrhs * NN + (size_t)r * NN + v] = acc[c];
+    for (int rb = 0; rb < 4; ++rb)
+        for (int cb = 0; cb < NT / 16; ++cb) {
+            int j = 16 * cb + (lane & 15);
+            if (j >= ncol) continue;
+            int cc = (col0 + j) / nrhs, r = (col0 + j) % nrhs;
+            for (int v = 0; v < 4; ++v) {
+                int row = 64 * wave + 16 * rb + Mma<T>::row(lane, v);
+                size_t o = (((size_t)O * NCH + c0 + cc) * nrhs + r) * NN + row;
+                size_t pe = ((((size_t)O * 2 + parity) * NCH + c0 + cc) * nrhs + r) * NN + row;
+                LC[o] = (T)((double)acc[rb][cb][v] + (double)PEND[pe]);
+            }
+        }
 }
 
 // L2L: PEND(child, h) = T_{oct,h}^T LC(parent) for the child's intervals 2(k+1)+h.
@@ -484,10 +640,12 @@ void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
         int k = alpha / FL.M - 1;
         int slot = k % F->WR;
         if (FL.nleaf > 0) {
+            PhaseScope ps(C->prof, TDBEM_PH_P2M, s);
             hipLaunchKernelGGL(k_p2m, dim3(FL.nleaf, nr), dim3(256), 0, s, FL.leaf_cells, FL.ebeg, FL.eend, k, FL.M,
                                FL.ls, C->d_Jring, C->ring, nr, F->Wm, FL.MM, slot, F->WR);
         }
         if (FL.nparent > 0) {
+            PhaseScope ps(C->prof, TDBEM_PH_M2M, s);
             FarLevel &CL = F->lev[l + 1];
             hipLaunchKernelGGL(k_m2m, dim3(FL.nparent, 2 * NCH, nr), dim3(NN), 0, s, FL.parent_cells, FL.child_beg,
                                FL.child_end, CL.ix, F->S1, CL.MM, (2 * k) % F->WR, (2 * k + 1) % F->WR, F->WR, FL.MM,
@@ -500,14 +658,29 @@ void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
         FarLevel &FL = F->lev[l];
         if (alpha % FL.M) continue;
         int k = alpha / FL.M - 1;
-        hipLaunchKernelGGL(k_m2l, dim3(FL.n, 2, nr), dim3(NN), 0, s, FL.n, FL.il_off, FL.il_src, FL.il_code, FL.MM,
-                           F->WR, k, F->W, FL.hs, FL.ht, C->c, FL.PEND, FL.LC, nr);
+        {
+            PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
+            if (nr == 1) {
+                if (FL.ntile > 0)
+                    hipLaunchKernelGGL((k_m2l_off<double, M2L_NT>), dim3(FL.ntile), dim3(256), 0, s, FL.tile_code,
+                                       FL.tile_kind, FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM,
+                                       F->WR, k, F->W, FL.hs, FL.ht, C->c, FL.YB);
+                hipLaunchKernelGGL((k_m2l_reduce<double>), dim3(FL.n, NCH), dim3(NN), 0, s, FL.n, FL.il_off, FL.YB,
+                                   FL.PEND, (k + 1) & 1, FL.LC);
+            } else {
+                hipLaunchKernelGGL((k_m2l_tgt<double, M2L_NT>), dim3(FL.n, 2, (4 * nr + M2L_NT - 1) / M2L_NT), dim3(256),
+                                   0, s, FL.il_off, FL.il_src, FL.il_code, FL.MM, F->WR, k, F->W, FL.hs, FL.ht, C->c,
+                                   FL.PEND, FL.LC, nr);
+            }
+        }
         if (FL.nparent > 0) {
+            PhaseScope ps(C->prof, TDBEM_PH_L2L, s);
             FarLevel &CL = F->lev[l + 1];
             hipLaunchKernelGGL(k_l2l, dim3(FL.nparent, 2 * NCH, nr), dim3(NN), 0, s, FL.parent_cells, FL.child_beg,
                                FL.child_end, CL.ix, F->S1, FL.LC, CL.PEND, nr);
         }
         if (FL.nleaf > 0) {
+            PhaseScope ps(C->prof, TDBEM_PH_L2P, s);
             hipLaunchKernelGGL(k_l2p, dim3(FL.nleaf), dim3(256), 0, s, FL.leaf_cells, FL.nleaf, FL.ebeg, FL.eend, k,
                                FL.M, FL.tw, C->cfg.zeta, F->El, FL.LC, F->FAR, F->FR, C->ne, nr, 0);
         }

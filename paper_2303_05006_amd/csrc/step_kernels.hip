@@ -7,6 +7,8 @@
 // so one pair's lag strip reads consecutive slots of one edge.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+
 #include "tdbem_internal.h"
 
 namespace tdbem {
@@ -261,18 +263,32 @@ int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit
             beta[r] = std::sqrt(beta[r]);
             if (!(beta[r] <= rtol * bn[r] || bn[r] == 0.0)) all = false;
         }
+        if (C->debug_gmres) {
+            fprintf(stderr, "gmres alpha=%d total=%d:", C->alpha, total);
+            for (int r = 0; r < nr; ++r) fprintf(stderr, " %.3e/%.3e", beta[r], bn[r]);
+            fprintf(stderr, "\n");
+        }
         if (all) { conv = true; break; }
+        // per-rhs Arnoldi length: a right-hand side stops contributing columns
+        // once its residual estimate meets the tolerance (or is already met)
+        std::vector<int> kr(nr, -1);
         std::vector<double> inv(nr);
-        for (int r = 0; r < nr; ++r) inv[r] = beta[r] > 0 ? 1.0 / beta[r] : 0.0;
+        for (int r = 0; r < nr; ++r) {
+            bool done = beta[r] <= rtol * bn[r] || bn[r] == 0.0;
+            inv[r] = (!done && beta[r] > 0) ? 1.0 / beta[r] : 0.0;
+            if (done) kr[r] = 0;
+        }
         TD_HIP(hipMemcpyAsync(dots, inv.data(), sizeof(double) * nr, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_scale_rhs, dim3(g), dim3(256), 0, s, ne, nr, dots, V, V);
         std::fill(gv.begin(), gv.end(), 0.0);
-        for (int r = 0; r < nr; ++r) gv[r] = beta[r];
+        for (int r = 0; r < nr; ++r) gv[r] = kr[r] == 0 ? 0.0 : beta[r];
         int k = 0;
         for (; k < m && total < maxit; ++k, ++total) {
             hipLaunchKernelGGL(k_scale_rows, dim3(g), dim3(256), 0, s, ne, nr, C->d_z0_dinv, V + k * vs, z);
             hipLaunchKernelGGL(k_spmv, dim3(g), dim3(256), 0, s, ne, nr, C->d_z0_ptr, C->d_z0_col, C->d_z0_val, z, w);
             std::vector<double> hsum((size_t)(k + 1) * nr, 0.0);
+            std::vector<double> wn0(nr);
+            mdot(1, w, w, wn0.data());
             for (int pass = 0; pass < 2; ++pass) {
                 mdot(k + 1, V, w, hd.data());
                 TD_HIP(hipMemcpyAsync(dots, hd.data(), sizeof(double) * (k + 1) * nr, hipMemcpyHostToDevice, s));
@@ -284,12 +300,16 @@ int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit
             std::vector<double> inv2(nr);
             for (int r = 0; r < nr; ++r) {
                 hn[r] = std::sqrt(hn[r]);
-                inv2[r] = hn[r] > 0 ? 1.0 / hn[r] : 0.0;
+                // frozen rhs, or an exact (happy) breakdown: no further direction
+                bool stop = kr[r] >= 0 || hn[r] <= 1e-15 * std::sqrt(wn0[r]);
+                inv2[r] = (!stop && hn[r] > 0) ? 1.0 / hn[r] : 0.0;
+                if (stop && kr[r] < 0) hn[r] = 0.0;
             }
             TD_HIP(hipMemcpyAsync(dots, inv2.data(), sizeof(double) * nr, hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_scale_rhs, dim3(g), dim3(256), 0, s, ne, nr, dots, w, V + (k + 1) * vs);
             bool all2 = true;
             for (int r = 0; r < nr; ++r) {
+                if (kr[r] >= 0) continue;
                 double *Hc = &H[((size_t)r * (m + 1)) * m];   // column-major (m+1) x m per rhs
                 for (int q = 0; q <= k; ++q) Hc[q + (size_t)k * (m + 1)] = hsum[(size_t)q * nr + r];
                 Hc[k + 1 + (size_t)k * (m + 1)] = hn[r];
@@ -308,17 +328,19 @@ int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit
                 double gk = gv[(size_t)k * nr + r];
                 gv[(size_t)k * nr + r] = c * gk;
                 gv[(size_t)(k + 1) * nr + r] = -sgn * gk;
-                if (!(std::fabs(gv[(size_t)(k + 1) * nr + r]) <= rtol * bn[r] || bn[r] == 0.0)) all2 = false;
+                if (std::fabs(gv[(size_t)(k + 1) * nr + r]) <= rtol * bn[r] || hn[r] == 0.0) kr[r] = k + 1;
+                else all2 = false;
             }
             if (all2) { ++k; ++total; break; }
         }
-        // y = H^{-1} g (upper triangular k x k), x += Dinv V y
+        // y = H^{-1} g (upper triangular kr x kr per rhs), x += Dinv V y
         std::vector<double> y((size_t)k * nr, 0.0);
         for (int r = 0; r < nr; ++r) {
+            int kk = kr[r] >= 0 ? kr[r] : k;
             double *Hc = &H[((size_t)r * (m + 1)) * m];
-            for (int q = k - 1; q >= 0; --q) {
+            for (int q = kk - 1; q >= 0; --q) {
                 double sacc = gv[(size_t)q * nr + r];
-                for (int t = q + 1; t < k; ++t) sacc -= Hc[q + (size_t)t * (m + 1)] * y[(size_t)t * nr + r];
+                for (int t = q + 1; t < kk; ++t) sacc -= Hc[q + (size_t)t * (m + 1)] * y[(size_t)t * nr + r];
                 double dgn = Hc[q + (size_t)q * (m + 1)];
                 y[(size_t)q * nr + r] = dgn != 0.0 ? sacc / dgn : 0.0;
             }

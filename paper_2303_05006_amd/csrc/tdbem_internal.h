@@ -80,6 +80,26 @@ struct GeoDev {
 
 struct FarState;  // IFMM device state (ifmm.hip)
 
+// per-phase timing with HIP event pairs recorded on the work stream
+struct Profiler {
+    bool on = false;
+    double ms[TDBEM_NPHASE] = {0};
+    int64_t count[TDBEM_NPHASE] = {0};
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+    void begin(int phase, hipStream_t s, hipEvent_t &e0);
+    void end(int phase, hipStream_t s, hipEvent_t e0);
+    void fold(hipStream_t s);
+    void clear();
+    ~Profiler();
+};
+struct PhaseScope {
+    Profiler &P; int ph; hipStream_t s; hipEvent_t e0 = nullptr;
+    PhaseScope(Profiler &P_, int ph_, hipStream_t s_) : P(P_), ph(ph_), s(s_) { if (P.on) P.begin(ph, s, e0); }
+    ~PhaseScope() { if (P.on && e0) P.end(ph, s, e0); }
+};
+
 }  // namespace tdbem
 
 struct tdbem_ctx {
@@ -92,6 +112,7 @@ struct tdbem_ctx {
     int alpha = 1;                  // next step
     int ring = 64;                  // history ring length (power of two)
     int last_iters = 0;
+    bool debug_gmres = false;       // TDBEM_DEBUG_GMRES=1: residuals of every restart cycle on stderr
     double setup_ms = 0;
     size_t dev_bytes = 0;
     std::vector<void *> allocs;
@@ -140,4 +161,5 @@ struct tdbem_ctx {
     int window = 0;                 // source intervals per M2L (mu + 1)
     int far_ring_need = 0;          // history ring length the far field needs
     tdbem::FarState *far = nullptr;
+    tdbem::Profiler prof;
 };

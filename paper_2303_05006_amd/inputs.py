@@ -180,7 +180,12 @@ def gaussian_pulse(f0, fbw, k=(0, 0, 1), p=(1, 0, 0), E0=1.0, r_max=1.0):
     so that the field is negligible (exp(-12.5)) on the body at t = 0."""
     sigma = 3.0 / (2.0 * math.pi * fbw)
     k = np.asarray(k, float); k = k / np.linalg.norm(k)
-    p = np.asarray(p, float); p = p - k * (p @ k); p = p / np.linalg.norm(p)
+    p = np.asarray(p, float); p = p - k * (p @ k)
+    if np.linalg.norm(p) < 1e-8:
+        # polarisation parallel to the direction: take a perpendicular one
+        a = np.array([0.0, 0.0, 1.0]) if abs(k[2]) < 0.9 else np.array([1.0, 0.0, 0.0])
+        p = a - k * (a @ k)
+    p = p / np.linalg.norm(p)
     return Pulse(k=tuple(k), p=tuple(p), E0=E0, f0=f0, sigma=sigma,
                  delay=5.0 * sigma + r_max / C0, kind="gauss")
 

@@ -22,10 +22,11 @@ MODE_DIRECT, MODE_IFMM = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
 GUESS_EXTRAP, GUESS_LEARNED = 0, 1
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
-    Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS = range(15)
+    Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT = range(17)
+PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other"]
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
-           "tdbem_query", "tdbem_near_rows", "tdbem_destroy", "tdbem_last_error"]
+           "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_destroy", "tdbem_last_error"]
 
 
 class TdbemError(RuntimeError):
@@ -65,6 +66,7 @@ def load():
         L.tdbem_reset.argtypes = [P]
         L.tdbem_query.argtypes = [P, i32, P]
         L.tdbem_near_rows.argtypes = [P, P, i32, i32, P]
+        L.tdbem_profile.argtypes = [P, i32]
         L.tdbem_destroy.argtypes = [P]
         L.tdbem_destroy.restype = None
         L.tdbem_last_error.restype = ctypes.c_char_p
@@ -185,6 +187,14 @@ class Solver:
         _check(load().tdbem_near_rows(self._h, rows.ctypes.data_as(ctypes.c_void_p), len(rows), int(G),
                                       out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def profile(self, enable=True):
+        _check(load().tdbem_profile(self._h, 1 if enable else 0))
+
+    def phase_times(self):
+        ms = self.query_array(Q_PHASE_MS, len(PHASES), np.float64)
+        cnt = self.query_array(Q_PHASE_COUNT, len(PHASES), np.int64)
+        return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(PHASES)}
 
     def gmres_iters(self):
         return self.query_i32(Q_GMRES_ITERS)
