@@ -65,6 +65,8 @@ void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 void launch_gather_vals(const double *val, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, bool *ok, hipStream_t s);
 size_t gmres_work_doubles(const tdbem_ctx *C, int maxit);
+bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s);
+size_t gmres_coop_work_doubles(int ne);
 
 template <typename T>
 static T *dalloc(tdbem_ctx *C, size_t n) {
@@ -138,6 +140,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->precision >= TDBEM_FP64 && cfg->precision <= TDBEM_BF16, TDBEM_EINVAL, "unknown precision");
     C->stream = (hipStream_t)cfg->stream;
     if (const char *dbg = std::getenv("TDBEM_DEBUG_GMRES")) C->debug_gmres = dbg[0] == '1';
+    if (const char *hs = std::getenv("TDBEM_HOST_GMRES")) C->use_coop = hs[0] != '1';
     C->nrhs = cfg->n_rhs;
     C->c = 1.0 / std::sqrt(cfg->eps * cfg->mu);
     C->eta = std::sqrt(cfg->mu / cfg->eps);
@@ -214,6 +217,11 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_z0_ptr = dupload(C, z0ptr);
     C->d_z0_col = dupload(C, z0col);
     C->d_z0_dinv = dupload(C, dinv);
+    {
+        std::vector<double> vald(C->z0_nnz);
+        for (int64_t q = 0; q < C->z0_nnz; ++q) vald[q] = z0v[q] * dinv[z0col[q]];
+        C->d_z0_vald = dupload(C, vald);
+    }
     // ---- near store (g >= 2): views into the coefficient array
     std::vector<int> nrow(ne + 1, 0), nj, ng0, nlen;
     std::vector<int64_t> noff;
@@ -257,7 +265,11 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_rhs = dalloc<double>(C, nv);
     C->d_x = dalloc<double>(C, nv);
     C->d_tmp = dalloc<double>(C, nv);
-    C->d_work = dalloc<double>(C, gmres_work_doubles(C, std::max(1, cfg->gmres_maxit)));
+    C->d_work = dalloc<double>(C, std::max(gmres_work_doubles(C, std::max(1, cfg->gmres_maxit)),
+                                           gmres_coop_work_doubles(ne)));
+    C->d_iflag = dalloc<int>(C, 4);
+    TD_HIP(hipHostMalloc((void **)&C->h_iflag, 4 * sizeof(int), hipHostMallocDefault));
+    if (const char *gb = std::getenv("TDBEM_GMRES_BLOCKS")) C->gmres_blocks = std::max(1, std::atoi(gb));
     C->d_scal = dalloc<double>(C, 64 * (size_t)C->nrhs);
     C->d_pulse = dalloc<double>(C, 11 * (size_t)C->nrhs);
     TD_HIP(hipMemsetAsync(C->d_Jring, 0, (size_t)ne * R * C->nrhs * sizeof(double), s));
@@ -290,7 +302,15 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
         bool ok = true;
         {
             PhaseScope ps(C->prof, TDBEM_PH_GMRES, s);
-            C->last_iters = gmres_solve(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, std::max(1, C->cfg.gmres_maxit), &ok, s);
+            const int maxit = std::max(1, C->cfg.gmres_maxit);
+            if (C->nrhs == 1 && C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s)) {
+                TD_HIP(hipMemcpyAsync(C->h_iflag, C->d_iflag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+                TD_HIP(hipStreamSynchronize(s));
+                C->last_iters = C->h_iflag[0];
+                ok = C->h_iflag[1] != 0;
+            } else {
+                C->last_iters = gmres_solve(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, &ok, s);
+            }
         }
         if (!ok) rc = TDBEM_ENOCONV;
     } else {
@@ -458,6 +478,7 @@ void tdbem_destroy(tdbem_ctx *C) {
     ifmm_destroy(C);
     for (void *p : C->allocs) (void)hipFree(p);
     if (C->h_scal) (void)hipHostFree(C->h_scal);
+    if (C->h_iflag) (void)hipHostFree(C->h_iflag);
     delete C;
 }
 

@@ -1,0 +1,277 @@
+// Device-resident restarted GMRES for Z0 x = b (one right-hand side), Section 2.5.
+//
+// One cooperative launch of a few large blocks runs the whole solve: right
+// Jacobi preconditioning, Arnoldi with classical Gram-Schmidt applied twice,
+// Givens rotations and the restart logic.  Grid-wide barriers separate the
+// phases that read other blocks' rows (SpMV) or other blocks' partial sums
+// (dot products).  Partial sums are written per block and every block reduces
+// them in the same fixed order, so all blocks hold bitwise-identical scalars
+// and take identical branches: every barrier is reached by every block, and
+// the loop trip counts are bounded by the iteration cap.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "tdbem_internal.h"
+
+namespace cg = cooperative_groups;
+
+namespace tdbem {
+
+static constexpr int GM_MAXV = 33;      // Krylov vectors per restart cycle (m + 1) plus one self product
+static constexpr int GM_THREADS = 1024;
+
+struct GmresArgs {
+    int ne, m, maxit;
+    double rtol;
+    const int *ptr, *col;
+    const double *val, *dinv;
+    const double *vald;   // Z0 with columns scaled by dinv (right Jacobi preconditioner folded in)
+    const double *b;
+    double *x;
+    double *V;        // [(m+1)][ne]
+    double *w0, *w1;  // ping-pong work vectors [ne]
+    double *part;     // [nblk][GM_MAXV]
+    int *out;         // [0] iterations, [1] converged
+};
+
+// per-thread partial sums of <V_j, w> for j < nv over this block's rows,
+// reduced over the block into part[round parity][blk][j].  The two buffers
+// alternate by round: a block reaches round r+2 only after every block has
+// passed the barrier of round r+1, i.e. finished reading round r.
+__device__ void block_dots(const GmresArgs &A, int rnd, int nv, const double *Vb, size_t vs, const double *w, int r0,
+                           int r1, double *red, bool self = false) {
+    double *part = A.part + (size_t)(rnd & 1) * gridDim.x * GM_MAXV;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ntot = nv + (self ? 1 : 0);
+    for (int j = 0; j < ntot; ++j) {
+        double v = 0.0;
+        const double *Vj = j < nv ? Vb + (size_t)j * vs : w;
+        for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) v += Vj[i] * w[i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[wave * GM_MAXV + j] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ntot) {
+        double s = 0.0;
+        for (int wv = 0; wv < GM_THREADS / 64; ++wv) s += red[wv * GM_MAXV + threadIdx.x];
+        part[(size_t)blockIdx.x * GM_MAXV + threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// sum of the per-block partials with a fixed tree (identical in every block):
+// thread (j, b) loads part[b][j], then 64-lane groups reduce over b
+__device__ void grid_reduce(const GmresArgs &A, int rnd, int nv, double *dst) {
+    const double *part = A.part + (size_t)(rnd & 1) * gridDim.x * GM_MAXV;
+    const int nb = gridDim.x;                       // <= 64 (launch-checked)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < nv; j += GM_THREADS / 64) {
+        double v = lane < nb ? part[(size_t)lane * GM_MAXV + j] : 0.0;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) dst[j] = v;
+    }
+    __syncthreads();
+}
+
+// y_i = sum_q a_q v[col_q] (+ scale) for the block's rows; 32 lanes per row so that
+// the row's loads are independent, shuffle reduction within the half-wave.
+// mode 0: y = A v;  mode 1: y = b - A v
+__device__ void block_spmv(const int *ptr, const int *col, const double *a, const double *v, double vscale,
+                           const double *b, double *y, int r0, int r1) {
+    const int hl = threadIdx.x & 31, hw = threadIdx.x >> 5;
+    const int NH = GM_THREADS / 32;
+    // four rows per half-wave in flight: all loads issued before the reductions
+    for (int i0 = r0; i0 < r1; i0 += 4 * NH) {
+        int ii[4], q0[4], q1[4];
+        double s[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ii[u] = i0 + u * NH + hw;
+            bool ok = ii[u] < r1;
+            q0[u] = ok ? ptr[ii[u]] : 0;
+            q1[u] = ok ? ptr[ii[u] + 1] : 0;
+            s[u] = 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            for (int q = q0[u] + hl; q < q1[u]; q += 32) s[u] += a[q] * v[col[q]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            for (int o = 16; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, 32);
+            if (hl == 0 && ii[u] < r1) y[ii[u]] = b ? b[ii[u]] - s[u] : s[u] * vscale;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
+    cg::grid_group grid = cg::this_grid();
+    __shared__ double red[(GM_THREADS / 64) * GM_MAXV];
+    __shared__ double h1[GM_MAXV], h2[GM_MAXV], sc[4];
+    __shared__ double H[GM_MAXV * GM_MAXV], cs[GM_MAXV], sn[GM_MAXV], gv[GM_MAXV + 1], y[GM_MAXV];
+    const int ne = A.ne, m = A.m;
+    const int nb = gridDim.x;
+    const int r0 = (int)((int64_t)ne * blockIdx.x / nb), r1 = (int)((int64_t)ne * (blockIdx.x + 1) / nb);
+    const size_t vs = (size_t)ne;
+    int rnd = 0;
+    // ||b||
+    block_dots(A, rnd, 1, A.b, vs, A.b, r0, r1, red);
+    grid.sync();
+    grid_reduce(A, rnd++, 1, sc);
+    const double bn = sqrt(sc[0]);
+    int total = 0;
+    bool conv = false;
+    while (true) {
+        // r0 = b - A x  -> V_0 (own rows), its norm
+        block_spmv(A.ptr, A.col, A.val, A.x, 1.0, A.b, A.V, r0, r1);
+        __syncthreads();
+        block_dots(A, rnd, 1, A.V, vs, A.V, r0, r1, red);
+        grid.sync();
+        grid_reduce(A, rnd++, 1, sc);
+        const double beta = sqrt(sc[0]);
+        if (beta <= A.rtol * bn || bn == 0.0) { conv = true; break; }
+        if (total >= A.maxit) break;
+        const double ib = 1.0 / beta;
+        for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) A.V[i] *= ib;
+        if (threadIdx.x == 0) {
+            for (int q = 0; q <= m; ++q) gv[q] = 0.0;
+            gv[0] = beta;
+        }
+        grid.sync();   // V_0 complete before any block's SpMV
+        int k = 0, kused = 0;
+        double hscale = 1.0;            // 1/h_{k,k-1}: V_k = w_prev * hscale
+        double *wprev = nullptr;
+        for (; k < m && total < A.maxit; ++k) {
+            ++total;
+            double *w = (k & 1) ? A.w1 : A.w0;
+            // w = A Dinv V_k, with V_k = wprev * hscale for k >= 1 (rows of other blocks)
+            if (k == 0) {
+                block_spmv(A.ptr, A.col, A.vald, A.V, 1.0, nullptr, w, r0, r1);
+            } else {
+                block_spmv(A.ptr, A.col, A.vald, wprev, hscale, nullptr, w, r0, r1);
+                for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) A.V[(size_t)k * vs + i] = wprev[i] * hscale;
+            }
+            __syncthreads();
+            // Gram-Schmidt with the norm in the same reduction: h = V^T w and |w|^2;
+            // |w - V h|^2 = |w|^2 - |h|^2 unless cancellation (DGKS criterion
+            // |w - V h|^2 < |w|^2 / 2), in which case a second pass is made
+            block_dots(A, rnd, k + 1, A.V, vs, w, r0, r1, red, true);
+            grid.sync();
+            grid_reduce(A, rnd++, k + 2, h1);
+            for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) {
+                double s = w[i];
+                for (int j = 0; j <= k; ++j) s -= h1[j] * A.V[(size_t)j * vs + i];
+                w[i] = s;
+            }
+            if (threadIdx.x == 0) {
+                double hh = 0.0;
+                for (int j = 0; j <= k; ++j) hh += h1[j] * h1[j];
+                double ww = h1[k + 1];
+                sc[0] = ww - hh;
+                sc[3] = (ww - hh < 0.5 * ww) ? 1.0 : 0.0;
+                for (int j = 0; j <= k; ++j) h2[j] = 0.0;
+            }
+            __syncthreads();
+            if (sc[3] != 0.0) {
+                block_dots(A, rnd, k + 1, A.V, vs, w, r0, r1, red, true);
+                grid.sync();
+                grid_reduce(A, rnd++, k + 2, h2);
+                for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) {
+                    double s = w[i];
+                    for (int j = 0; j <= k; ++j) s -= h2[j] * A.V[(size_t)j * vs + i];
+                    w[i] = s;
+                }
+                if (threadIdx.x == 0) {
+                    double hh = 0.0;
+                    for (int j = 0; j <= k; ++j) hh += h2[j] * h2[j];
+                    sc[0] = h2[k + 1] - hh;
+                }
+                __syncthreads();
+            }
+            if (threadIdx.x == 0 && sc[0] < 0.0) sc[0] = 0.0;
+            __syncthreads();
+            // Hessenberg column, rotations (every block, identically)
+            if (threadIdx.x == 0) {
+                double hn = sqrt(sc[0]);
+                for (int q = 0; q <= k; ++q) H[q * GM_MAXV + k] = h1[q] + h2[q];
+                double hk1 = hn;
+                for (int q = 0; q < k; ++q) {
+                    double a = H[q * GM_MAXV + k], bb = H[(q + 1) * GM_MAXV + k];
+                    H[q * GM_MAXV + k] = cs[q] * a + sn[q] * bb;
+                    H[(q + 1) * GM_MAXV + k] = -sn[q] * a + cs[q] * bb;
+                }
+                double a = H[k * GM_MAXV + k];
+                double rr = sqrt(a * a + hk1 * hk1);
+                double c = rr > 0 ? a / rr : 1.0, s = rr > 0 ? hk1 / rr : 0.0;
+                cs[k] = c; sn[k] = s;
+                H[k * GM_MAXV + k] = rr;
+                double gk = gv[k];
+                gv[k] = c * gk;
+                gv[k + 1] = -s * gk;
+                sc[1] = (fabs(gv[k + 1]) <= A.rtol * bn || hn == 0.0) ? 1.0 : 0.0;
+                sc[2] = hn > 0.0 ? 1.0 / hn : 0.0;
+            }
+            __syncthreads();
+            hscale = sc[2];
+            wprev = w;
+            kused = k + 1;
+            if (sc[1] != 0.0) break;
+        }
+        // y = H^{-1} g, x += Dinv V y (own rows)
+        if (threadIdx.x == 0) {
+            for (int q = kused - 1; q >= 0; --q) {
+                double s = gv[q];
+                for (int t = q + 1; t < kused; ++t) s -= H[q * GM_MAXV + t] * y[t];
+                double d = H[q * GM_MAXV + q];
+                y[q] = d != 0.0 ? s / d : 0.0;
+            }
+        }
+        __syncthreads();
+        for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) {
+            double s = 0.0;
+            for (int j = 0; j < kused; ++j) s += y[j] * A.V[(size_t)j * vs + i];
+            A.x[i] += A.dinv[i] * s;
+        }
+        grid.sync();   // x complete before the next residual
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.out[0] = total;
+        A.out[1] = conv ? 1 : 0;
+    }
+}
+
+// Launch the cooperative solve; returns false if the device cannot co-schedule
+// the grid (the caller then uses the host-driven solver).
+bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s) {
+    int dev = 0;
+    TD_HIP(hipGetDevice(&dev));
+    int coop = 0;
+    TD_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    if (!coop) return false;
+    int per_cu = 0;
+    TD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_gmres_coop, GM_THREADS, 0));
+    int ncu = 0;
+    TD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    int nblk = std::min(std::min(C->gmres_blocks, 64), per_cu * ncu);
+    if (nblk < 1) return false;
+    const int m = std::min(GM_MAXV - 1, std::max(1, maxit));
+    double *V = C->d_work;
+    size_t vs = (size_t)C->ne;
+    GmresArgs A;
+    A.ne = C->ne; A.m = m; A.maxit = maxit; A.rtol = rtol;
+    A.ptr = C->d_z0_ptr; A.col = C->d_z0_col; A.val = C->d_z0_val; A.dinv = C->d_z0_dinv; A.vald = C->d_z0_vald;
+    A.b = b; A.x = x;
+    A.V = V;
+    A.w0 = V + (size_t)(m + 1) * vs;
+    A.w1 = A.w0 + vs;
+    A.part = A.w1 + vs;
+    A.out = C->d_iflag;
+    void *args[] = {&A};
+    TD_HIP(hipLaunchCooperativeKernel((const void *)k_gmres_coop, dim3(nblk), dim3(GM_THREADS), args, 0, s));
+    return true;
+}
+
+size_t gmres_coop_work_doubles(int ne) {
+    return (size_t)(GM_MAXV + 2) * ne + (size_t)2 * 4096 * GM_MAXV;
+}
+
+}  // namespace tdbem

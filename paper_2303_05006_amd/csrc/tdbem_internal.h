@@ -140,6 +140,7 @@ struct tdbem_ctx {
     int64_t z0_nnz = 0;
     int *d_z0_ptr = nullptr, *d_z0_col = nullptr;
     double *d_z0_val = nullptr, *d_z0_dinv = nullptr;
+    double *d_z0_vald = nullptr;    // Z0 with columns scaled by the Jacobi inverse
 
     // march state
     double *d_Jring = nullptr;      // [ne][ring][nrhs]
@@ -150,6 +151,10 @@ struct tdbem_ctx {
     double *h_scal = nullptr;       // pinned host mirror
     double *d_pulse = nullptr;      // [nrhs][11]
     double *d_tmp = nullptr;        // [ne][nrhs] scratch (canonical order io)
+    int *d_iflag = nullptr;         // device solver status: iterations, converged
+    int *h_iflag = nullptr;         // pinned host mirror
+    int gmres_blocks = 64;          // blocks of the cooperative solve
+    bool use_coop = true;           // device-resident solve for one right-hand side
 
     // host copies of the coefficient pair structure (leaf order, sorted by row)
     std::vector<int> hp_i, hp_j, hp_lo, hp_hi;

@@ -101,3 +101,33 @@ def test_direct_march_matches_oracle_320_triangles():
     print(f"marched rel L2 error {rel:.2e}")
     assert rel < 1e-10
     S.close()
+
+
+def test_device_gmres_matches_host_gmres():
+    """The cooperative device-resident Z0 solve against the host-driven one."""
+    import os
+    torch = _torch()
+    w = workload("conv320", nt=120)
+    outs = []
+    for host in ("1", "0"):
+        os.environ["TDBEM_HOST_GMRES"] = host
+        try:
+            S = tdbem.Solver(w.verts, w.tris, tdbem.Config(dt=w.dt, mode=tdbem.MODE_DIRECT, gmres_rtol=1e-12,
+                                                           gmres_maxit=100))
+        finally:
+            os.environ.pop("TDBEM_HOST_GMRES", None)
+        ne = S.ne
+        V = torch.zeros(ne, dtype=torch.float64, device="cuda")
+        J = torch.zeros(ne, dtype=torch.float64, device="cuda")
+        out, its = [], []
+        for a in range(1, w.nt):
+            S.incident(w.pulses, a, V)
+            S.step(V, J)
+            out.append(J.cpu().numpy())
+            its.append(S.gmres_iters())
+        outs.append((np.array(out), its))
+        S.close()
+    (Jh, ih), (Jd, idv) = outs
+    rel = np.linalg.norm(Jd - Jh) / np.linalg.norm(Jh)
+    print(f"device vs host GMRES: rel {rel:.2e}, iterations {sum(idv)} vs {sum(ih)}")
+    assert rel < 1e-10
