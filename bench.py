@@ -149,7 +149,7 @@ def main():
             lags = min(win, k + 1)
             m2l_flops += info["nilist"][l] * lags * 7 * 2.0 * 256 * 256 * nr
     vb = 8 if prec == tdbem.FP64 else 4
-    near_bytes = K * (info["near_nnz"] * vb + info["near_pairs"] * 20 + ne * 8 * nr)
+    near_bytes = K * (info["near_nnz"] * vb + info["near_pairs"] * 8 + ne * 8 * nr)
     kernels = {}
     t_m2l = ph["m2l"][0] * 1e-3
     t_near = ph["near"][0] * 1e-3

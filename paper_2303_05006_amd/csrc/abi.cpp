@@ -62,6 +62,7 @@ void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hip
 void launch_ring_put(const tdbem_ctx *C, int slot, const double *x, hipStream_t s);
 void launch_extrap(const tdbem_ctx *C, int alpha, double *x, hipStream_t s);
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+void launch_near_to_jds(const tdbem_ctx *C, const int64_t *src_off, const double *src, hipStream_t s);
 void launch_gather_vals(const double *val, const int64_t *idx, int64_t n, double *out, hipStream_t s);
 int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, bool *ok, hipStream_t s);
 size_t gmres_work_doubles(const tdbem_ctx *C, int maxit);
@@ -222,32 +223,59 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
         for (int64_t q = 0; q < C->z0_nnz; ++q) vald[q] = z0v[q] * dinv[z0col[q]];
         C->d_z0_vald = dupload(C, vald);
     }
-    // ---- near store (g >= 2): views into the coefficient array
-    std::vector<int> nrow(ne + 1, 0), nj, ng0, nlen;
-    std::vector<int64_t> noff;
-    nj.reserve(np); ng0.reserve(np); nlen.reserve(np); noff.reserve(np);
+    // ---- near store (g >= 2) in the jagged-diagonal layout
+    std::vector<int> nrow(ne + 1, 0), nj, ngl;
+    std::vector<int64_t> nsrc, vbase(ne, 0);
+    nj.reserve(np); ngl.reserve(np); nsrc.reserve(np);
+    int L = 0;
     int64_t nnz2 = 0;
-    for (int64_t p = 0; p < np; ++p) {
-        int g0 = std::max(glo[p], 2);
-        int len = ghi[p] - g0 + 1;
-        if (len <= 0) continue;
-        nj.push_back(pj[p]); ng0.push_back(g0); nlen.push_back(len);
-        noff.push_back(off[p] + (g0 - glo[p]));
-        nrow[pi[p] + 1]++;
-        nnz2 += len;
+    {
+        std::vector<int64_t> order;
+        int64_t p = 0;
+        for (int i = 0; i < ne; ++i) {
+            order.clear();
+            int64_t pe = p;
+            while (pe < np && pi[pe] == i) ++pe;
+            for (int64_t q = p; q < pe; ++q)
+                if (ghi[q] >= std::max(glo[q], 2)) order.push_back(q);
+            auto len_of = [&](int64_t q) { return ghi[q] - std::max(glo[q], 2) + 1; };
+            std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return len_of(a) > len_of(b); });
+            vbase[i] = nnz2;
+            for (int64_t q : order) {
+                int g0 = std::max(glo[q], 2), len = len_of(q);
+                TD_REQUIRE(g0 < 65536 && len < 32768, TDBEM_EINVAL, "lag range too long for the near-field store");
+                nj.push_back(pj[q]);
+                ngl.push_back(g0 | (len << 16));
+                nsrc.push_back(off[q] + (g0 - glo[q]));
+                nnz2 += len;
+                L = std::max(L, len);
+            }
+            nrow[i + 1] = nrow[i] + (int)order.size();
+            p = pe;
+        }
     }
-    for (int i = 0; i < ne; ++i) nrow[i + 1] += nrow[i];
+    TD_REQUIRE(L <= 512, TDBEM_EINVAL, "near-field lag strips longer than 512 steps");
+    std::vector<int> nl((size_t)ne * std::max(L, 1), 0);
+    for (int i = 0; i < ne; ++i)
+        for (int q = nrow[i]; q < nrow[i + 1]; ++q) {
+            int len = ngl[q] >> 16;
+            for (int l = 0; l < len; ++l) nl[(size_t)i * L + l]++;
+        }
+    C->near_L = std::max(L, 1);
     C->near_pairs = (int64_t)nj.size();
     C->near_nnz = nnz2;
     C->d_nrow_ptr = dupload(C, nrow);
+    C->d_nrow_vbase = dupload(C, vbase);
+    C->d_nl = dupload(C, nl);
     C->d_npair_j = dupload(C, nj);
-    C->d_npair_g0 = dupload(C, ng0);
-    C->d_npair_len = dupload(C, nlen);
-    C->d_npair_off = dupload(C, noff);
-    C->d_nval = d_val;
-    if (cfg->precision != TDBEM_FP64) {
-        C->d_nval32 = dalloc<float>(C, nnz);
-        launch_to_f32(d_val, C->d_nval32, nnz, s);
+    C->d_npair_gl = dupload(C, ngl);
+    C->d_coef = d_val;
+    C->d_nval = dalloc<double>(C, nnz2);
+    if (cfg->precision != TDBEM_FP64) C->d_nval32 = dalloc<float>(C, nnz2);
+    {
+        int64_t *d_src = dupload(C, nsrc);
+        launch_near_to_jds(C, d_src, d_val, s);
+        TD_HIP(hipStreamSynchronize(s));
     }
     C->max_lag = maxlag;
     // keep host copies of the pair structure for inspection
@@ -445,7 +473,7 @@ int tdbem_near_rows(tdbem_ctx *C, const int32_t *rows, int32_t n, int32_t G, dou
         const int ne = C->ne;
         std::memset(out, 0, sizeof(double) * (size_t)n * ne * G);
         std::vector<double> val(C->hp_nnz);
-        TD_HIP(hipMemcpy(val.data(), C->d_nval, C->hp_nnz * sizeof(double), hipMemcpyDeviceToHost));
+        TD_HIP(hipMemcpy(val.data(), C->d_coef, C->hp_nnz * sizeof(double), hipMemcpyDeviceToHost));
         // row ranges in the (sorted by i) pair list
         for (int r = 0; r < n; ++r) {
             TD_REQUIRE(rows[r] >= 0 && rows[r] < ne, TDBEM_EINVAL, "row out of range");

@@ -14,75 +14,136 @@
 namespace tdbem {
 
 // ---------------------------------------------------------------- near field
-// One 64-wide wavefront per target row; lanes stride over the row's pairs and
-// walk each pair's contiguous lag strip; butterfly reduction over the wave.
-template <typename VT>
-__global__ void __launch_bounds__(256) k_near_rhs1(int ne, const int *__restrict__ row_ptr, const int *__restrict__ pj,
-                                                   const int *__restrict__ pg0, const int *__restrict__ plen,
-                                                   const int64_t *__restrict__ poff, const VT *__restrict__ val,
-                                                   const double *__restrict__ ring, int ring_mask, int alpha,
-                                                   double *__restrict__ out, double scale_out) {
-    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
-    if (wave >= ne) return;
-    int R = ring_mask + 1;
-    double acc = 0.0;
-    for (int p = row_ptr[wave] + lane; p < row_ptr[wave + 1]; p += 64) {
-        int j = pj[p], g0 = pg0[p], len = plen[p];
-        const VT *v = val + poff[p];
-        const double *J = ring + (size_t)j * R;
-        int b = alpha - g0;
-        for (int l = 0; l < len; ++l) acc += (double)v[l] * J[(b - l) & ring_mask];
+// Jagged-diagonal layout per target row: the row's pairs are sorted by the
+// length of their lag strip (longest first) and the l-th coefficient of every
+// pair with a strip longer than l is stored contiguously at off_l + p, so the
+// lanes of a wavefront read consecutive values at every lag.  nl[row][l] is the
+// number of pairs with a strip longer than l; off_l is its prefix sum.
+static constexpr int NEAR_LMAX = 512;
+
+__device__ __forceinline__ int near_offsets(const int *nl_row, int L, int lane, int *off) {
+    // exclusive prefix sums of nl_row[0..L) into off[], 64 lags per pass
+    int carry = 0;
+    for (int l0 = 0; l0 < L; l0 += 64) {
+        int l = l0 + lane;
+        int v = l < L ? nl_row[l] : 0;
+        int x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (l < L) off[l] = carry + x - v;
+        carry += __shfl(x, 63, 64);
     }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) out[wave] = scale_out * acc;
+    return carry;
 }
 
-// batched right-hand sides: one wavefront per (row, 64-rhs group); lanes are rhs
 template <typename VT>
-__global__ void __launch_bounds__(256) k_near_rhsN(int ne, int nrhs, const int *__restrict__ row_ptr, const int *__restrict__ pj,
-                                                   const int *__restrict__ pg0, const int *__restrict__ plen,
-                                                   const int64_t *__restrict__ poff, const VT *__restrict__ val,
+__global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
+                                                   const int *__restrict__ nl, int L, const int *__restrict__ pj,
+                                                   const int *__restrict__ pgl, const VT *__restrict__ val,
                                                    const double *__restrict__ ring, int ring_mask, int alpha,
-                                                   double *__restrict__ out, double scale_out) {
-    int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
-    int ngrp = (nrhs + 63) >> 6;
-    if (wave >= ne * ngrp) return;
-    int row = wave / ngrp, r = (wave % ngrp) * 64 + lane;
-    bool act = r < nrhs;
-    int R = ring_mask + 1;
+                                                   double *__restrict__ out) {
+    __shared__ int offs[4][NEAR_LMAX];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + wv;
+    if (row >= ne) return;
+    int *off = offs[wv];
+    near_offsets(nl + (size_t)row * L, L, lane, off);
+    const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
+    const VT *v = val + row_vbase[row];
+    const int R = ring_mask + 1;
     double acc = 0.0;
-    for (int p = row_ptr[row]; p < row_ptr[row + 1]; ++p) {
-        int j = pj[p], g0 = pg0[p], len = plen[p];
-        const VT *v = val + poff[p];
-        const double *J = ring + (size_t)j * R * nrhs;
-        int b = alpha - g0;
-        if (act)
-            for (int l = 0; l < len; ++l) acc += (double)v[l] * J[(size_t)((b - l) & ring_mask) * nrhs + r];
+    for (int p = lane; p < np; p += 64) {
+        const int j = pj[pb + p], gl = pgl[pb + p];
+        const int g0 = gl & 0xffff, len = gl >> 16;
+        const double *J = ring + (size_t)j * R;
+        const int b = alpha - g0;
+        for (int l = 0; l < len; ++l) acc += (double)v[off[l] + p] * J[(b - l) & ring_mask];
     }
-    if (act) out[(size_t)row * nrhs + r] = scale_out * acc;
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) out[row] = acc;
+}
+
+// batched right-hand sides: one wavefront per (row, group of 64 rhs); lanes are rhs
+template <typename VT>
+__global__ void __launch_bounds__(256) k_near_jdsN(int ne, int nrhs, const int *__restrict__ row_ptr,
+                                                   const int64_t *__restrict__ row_vbase, const int *__restrict__ nl, int L,
+                                                   const int *__restrict__ pj, const int *__restrict__ pgl,
+                                                   const VT *__restrict__ val, const double *__restrict__ ring, int ring_mask,
+                                                   int alpha, double *__restrict__ out) {
+    __shared__ int offs[4][NEAR_LMAX];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ngrp = (nrhs + 63) >> 6;
+    const int wave = blockIdx.x * 4 + wv;
+    if (wave >= ne * ngrp) return;
+    const int row = wave / ngrp, r = (wave % ngrp) * 64 + lane;
+    int *off = offs[wv];
+    near_offsets(nl + (size_t)row * L, L, lane, off);
+    const bool act = r < nrhs;
+    const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
+    const VT *v = val + row_vbase[row];
+    const int R = ring_mask + 1;
+    double acc = 0.0;
+    for (int p = 0; p < np; ++p) {
+        const int j = pj[pb + p], gl = pgl[pb + p];
+        const int g0 = gl & 0xffff, len = gl >> 16;
+        const double *J = ring + (size_t)j * R * nrhs + (act ? r : 0);
+        const int b = alpha - g0;
+        for (int l = 0; l < len; ++l) acc += (double)v[off[l] + p] * J[(size_t)((b - l) & ring_mask) * nrhs];
+    }
+    if (act) out[(size_t)row * nrhs + r] = acc;
+}
+
+// scatter the pair-major coefficient strips into the jagged-diagonal layout
+template <typename VT>
+__global__ void k_near_to_jds(int ne, const int *row_ptr, const int64_t *row_vbase, const int *nl, int L,
+                              const int *pgl, const int64_t *src_off, const double *src, VT *dst) {
+    __shared__ int offs[4][NEAR_LMAX];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + wv;
+    if (row >= ne) return;
+    int *off = offs[wv];
+    near_offsets(nl + (size_t)row * L, L, lane, off);
+    const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
+    VT *d = dst + row_vbase[row];
+    for (int p = lane; p < np; p += 64) {
+        const int len = pgl[pb + p] >> 16;
+        const double *s = src + src_off[pb + p];
+        for (int l = 0; l < len; ++l) d[off[l] + p] = (VT)s[l];
+    }
+}
+
+void launch_near_to_jds(const tdbem_ctx *C, const int64_t *src_off, const double *src, hipStream_t s) {
+    unsigned nb = (unsigned)((C->ne + 3) / 4);
+    hipLaunchKernelGGL(k_near_to_jds<double>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+                       C->d_nl, C->near_L, C->d_npair_gl, src_off, src, C->d_nval);
+    if (C->d_nval32)
+        hipLaunchKernelGGL(k_near_to_jds<float>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+                           C->d_nl, C->near_L, C->d_npair_gl, src_off, src, C->d_nval32);
+    TD_HIP(hipGetLastError());
 }
 
 void launch_near(const tdbem_ctx *C, int alpha, double *out, double scale, hipStream_t s) {
-    int bs = 256;
+    (void)scale;
+    const bool f64 = C->cfg.precision == TDBEM_FP64;
     if (C->nrhs == 1) {
-        unsigned nb = (unsigned)(((int64_t)C->ne * 64 + bs - 1) / bs);
-        if (C->cfg.precision == TDBEM_FP64)
-            hipLaunchKernelGGL(k_near_rhs1<double>, dim3(nb), dim3(bs), 0, s, C->ne, C->d_nrow_ptr, C->d_npair_j, C->d_npair_g0,
-                               C->d_npair_len, C->d_npair_off, C->d_nval, C->d_Jring, C->ring - 1, alpha, out, scale);
+        unsigned nb = (unsigned)((C->ne + 3) / 4);
+        if (f64)
+            hipLaunchKernelGGL(k_near_jds1<double>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval, C->d_Jring, C->ring - 1, alpha, out);
         else
-            hipLaunchKernelGGL(k_near_rhs1<float>, dim3(nb), dim3(bs), 0, s, C->ne, C->d_nrow_ptr, C->d_npair_j, C->d_npair_g0,
-                               C->d_npair_len, C->d_npair_off, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out, scale);
+            hipLaunchKernelGGL(k_near_jds1<float>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out);
     } else {
         int ngrp = (C->nrhs + 63) / 64;
-        unsigned nb = (unsigned)(((int64_t)C->ne * ngrp * 64 + bs - 1) / bs);
-        if (C->cfg.precision == TDBEM_FP64)
-            hipLaunchKernelGGL(k_near_rhsN<double>, dim3(nb), dim3(bs), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_npair_j,
-                               C->d_npair_g0, C->d_npair_len, C->d_npair_off, C->d_nval, C->d_Jring, C->ring - 1, alpha, out, scale);
+        unsigned nb = (unsigned)(((int64_t)C->ne * ngrp + 3) / 4);
+        if (f64)
+            hipLaunchKernelGGL(k_near_jdsN<double>, dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_nrow_vbase,
+                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval, C->d_Jring, C->ring - 1, alpha, out);
         else
-            hipLaunchKernelGGL(k_near_rhsN<float>, dim3(nb), dim3(bs), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_npair_j,
-                               C->d_npair_g0, C->d_npair_len, C->d_npair_off, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out, scale);
+            hipLaunchKernelGGL(k_near_jdsN<float>, dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_nrow_vbase,
+                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out);
     }
     TD_HIP(hipGetLastError());
 }

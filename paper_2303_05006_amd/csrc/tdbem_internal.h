@@ -125,15 +125,17 @@ struct tdbem_ctx {
     double *d_elen = nullptr;
     int *d_perm = nullptr;          // leaf -> canonical
 
-    // near-field store (g >= 2), row-major by target (leaf order)
+    // near-field store (g >= 2): jagged-diagonal layout per target row (leaf order)
     int64_t near_pairs = 0, near_nnz = 0;
-    int *d_nrow_ptr = nullptr;      // [ne+1] pair ranges per row
+    int *d_nrow_ptr = nullptr;      // [ne+1] pair ranges per row (pairs sorted by strip length)
+    int64_t *d_nrow_vbase = nullptr;// [ne] first value of each row
+    int *d_nl = nullptr;            // [ne][near_L] pairs with a strip longer than l
+    int near_L = 0;                 // longest strip
     int *d_npair_j = nullptr;       // [pairs] source edge (leaf order)
-    int *d_npair_g0 = nullptr;      // [pairs] first stored lag (>= 2)
-    int *d_npair_len = nullptr;     // [pairs]
-    int64_t *d_npair_off = nullptr; // [pairs] value offset
+    int *d_npair_gl = nullptr;      // [pairs] first stored lag | strip length << 16
     double *d_nval = nullptr;       // [nnz] FP64 values
     float *d_nval32 = nullptr;      // [nnz] FP32 copy (precision forms)
+    double *d_coef = nullptr;       // pair-major coefficients of every pair (all lags), for inspection
     int max_lag = 0;
 
     // Z0 = Zt^(1) CSR (leaf order)
