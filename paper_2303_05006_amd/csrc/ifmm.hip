@@ -24,6 +24,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "ifmm.h"
 
@@ -33,7 +34,7 @@ static constexpr int P = 4;        // interpolation points per axis and in time
 static constexpr int NS = P * P * P;
 static constexpr int NN = NS * P;   // 256
 static constexpr int NCH = 7;
-static constexpr int M2L_NT = 32;   // columns per M2L tile
+static constexpr int M2L_NT = 64;  // columns per M2L tile
 
 struct FarLevel {
     int n = 0, M = 0;
@@ -374,10 +375,15 @@ __global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int 
 // acc[256 x NT] += K(off, lag) X[256 x NT] on the matrix cores.  Rows are target
 // nodes (a, m), columns of X are source moment vectors indexed (b, n); the
 // 16x16x4 instruction's k-step of 4 is one source node b and its 4 time nodes.
-// K is generated per lane: node offsets lie on a lattice of spacing (2/3) h_s in
-// space and (2/3) h_t in time, x_a - y_b = (2/3) h_s ((a - b) - 3 off) and
-// t_m - s_n = (2/3) h_t (3 lag + m - n); distances come from LDS tables indexed
-// by the integer |(a - b) - 3 off|^2 (at most 3 * 12^2 for |off| <= 3).
+// Node offsets lie on a lattice of spacing (2/3) h_s in space and (2/3) h_t in
+// time: x_a - y_b = (2/3) h_s ((a - b) - 3 off), t_m - s_n = (2/3) h_t (3 lag +
+// m - n).  For one (offset, lag) the operator therefore takes only 7^3 * 7
+// distinct values, indexed by a - b in [-3, 3]^3 and m - n in [-3, 3]: the block
+// tabulates them in LDS once per lag and every lane reads its A operand from the
+// table at an address that is its own row base minus a constant of the k-step.
+// T is the arithmetic type of the operator and the products (FP64 form: double
+// with the f64 instruction; FP32 form: float with the f32 instruction); the
+// moments and the accumulated local expansions stay in FP64 in HBM.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -393,162 +399,215 @@ template <> struct Mma<float> {
     __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }      // output layout of the f32 form
 };
 
-static constexpr int QMAX = 433;       // |v|^2 <= 3 * 12^2
-static constexpr int WMAX = 64;        // 3 lag + m - n < 3 W + 3
+static constexpr int KTAB = 2401;          // 7^3 spatial differences x 7 time differences
+static constexpr int KTAB_MID = 1197;      // table index of a - b = (0, 0, 0), m - n = -3
+static constexpr int M2L_THREADS = 512;    // 8 wavefronts: 4 row blocks of 64 x 2 column halves
 
-struct M2LTables {
-    double r[QMAX], ir[QMAX];
-    double ct[WMAX];
-};
-
-__device__ void m2l_tables(M2LTables &tb, double hs, double ht, double cl, int tid) {
-    const double gs = hs * (2.0 / (P - 1)), gt = ht * (2.0 / (P - 1));
-    for (int q = tid; q < QMAX; q += blockDim.x) {
-        double r = gs * sqrt((double)q);
-        tb.r[q] = r;
-        tb.ir[q] = q > 0 ? 1.0 / r : 0.0;
+// operator table of one (offset, lag): tab[((d1 + 3) * 7 + d2 + 3) * 7 + d3 + 3) * 7 + w + 3] =
+// kernel at spatial lattice vector d - 3 off and time lattice 3 lag + w.
+// kind 0: dU/dt = 2c (c tau - r)_+ / r; kind 1: U = (c tau - r)_+^2 / r.
+template <typename T>
+__device__ void m2l_table(T *tab, int ox, int oy, int oz, int lag, int kind, double gs, double cgt, double c2) {
+    for (int e = threadIdx.x; e < KTAB; e += blockDim.x) {
+        const int w = e % 7 - 3, d = e / 7;
+        const int v1 = d / 49 - 3 - 3 * ox, v2 = (d / 7) % 7 - 3 - 3 * oy, v3 = d % 7 - 3 - 3 * oz;
+        const double r = gs * sqrt((double)(v1 * v1 + v2 * v2 + v3 * v3));
+        const double u = cgt * (3 * lag + w) - r;
+        double kv = 0.0;
+        if (u > 0.0 && r > 0.0) kv = kind == 0 ? c2 * u / r : u * u / r;
+        tab[e] = (T)kv;
     }
-    for (int w = tid; w < WMAX; w += blockDim.x) tb.ct[w] = cl * gt * w;
 }
 
-// one operator application: X (LDS, [NN][NT + 1]) for offset (ox, oy, oz) and lag
-template <typename T, int NT>
-__device__ __forceinline__ void m2l_apply(typename Mma<T>::acc_t (&acc)[4][NT / 16], const T (*X)[NT + 1],
-                                          const M2LTables &tb, int ox, int oy, int oz, int lag, int kind, double cl2,
-                                          int wave, int lane) {
+// per lane: table index of its rows at b = 0, minus KTAB_MID (k-step ks = b reads at
+// base + KTAB_MID - 7 * (49 b1 + 7 b2 + b3), always inside [0, KTAB))
+__device__ __forceinline__ void m2l_row_base(int (&base)[4], int wr, int lane) {
     const int n = lane >> 4;
-    int da[4][3], wv[4];
+#pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-        int row = 64 * wave + 16 * rb + (lane & 15);
-        int a = row >> 2, m = row & 3;
-        da[rb][0] = (a >> 4) - 3 * ox;
-        da[rb][1] = ((a >> 2) & 3) - 3 * oy;
-        da[rb][2] = (a & 3) - 3 * oz;
-        wv[rb] = 3 * lag + m - n;
+        const int row = 64 * wr + 16 * rb + (lane & 15);
+        const int a = row >> 2, m = row & 3;
+        base[rb] = (((((a >> 4) + 3) * 7 + ((a >> 2) & 3) + 3) * 7 + (a & 3) + 3) * 7 + m - n + 3) - KTAB_MID;
     }
-    for (int ks = 0; ks < NS; ++ks) {
-        const int b1 = ks >> 4, b2 = (ks >> 2) & 3, b3 = ks & 3;
-        T bv[NT / 16];
-        for (int cb = 0; cb < NT / 16; ++cb) bv[cb] = X[4 * ks + n][16 * cb + (lane & 15)];
-        for (int rb = 0; rb < 4; ++rb) {
-            int d1 = da[rb][0] - b1, d2 = da[rb][1] - b2, d3 = da[rb][2] - b3;
-            int q = d1 * d1 + d2 * d2 + d3 * d3;
-            double u = tb.ct[wv[rb]] - tb.r[q];
-            double kv = u > 0.0 ? (kind == 0 ? cl2 * u * tb.ir[q] : u * u * tb.ir[q]) : 0.0;
-            T av = (T)kv;
-            for (int cb = 0; cb < NT / 16; ++cb) acc[rb][cb] = Mma<T>::op(av, bv[cb], acc[rb][cb]);
+}
+
+// acc (this wave's 64 rows x 32 columns) += K X for the table in LDS
+template <typename T>
+__device__ __forceinline__ void m2l_apply(typename Mma<T>::acc_t (&acc)[4][2], const T (*X)[M2L_NT + 1],
+                                          const T *tab, const int (&base)[4], int wc, int lane) {
+    const int n = lane >> 4, col = 32 * wc + (lane & 15);
+#pragma unroll
+    for (int b1 = 0; b1 < 4; ++b1)
+#pragma unroll
+        for (int b2 = 0; b2 < 4; ++b2)
+#pragma unroll
+            for (int b3 = 0; b3 < 4; ++b3) {
+                const int ks = (b1 * 4 + b2) * 4 + b3;
+                const int toff = KTAB_MID - 7 * ((b1 * 7 + b2) * 7 + b3);
+                const T bv0 = X[4 * ks + n][col], bv1 = X[4 * ks + n][col + 16];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const T kv = tab[base[rb] + toff];
+                    acc[rb][0] = Mma<T>::op(kv, bv0, acc[rb][0]);
+                    acc[rb][1] = Mma<T>::op(kv, bv1, acc[rb][1]);
+                }
+            }
+}
+
+// X[xr][j] = MM[cbase[j] + loff] for the columns j = xj, xj + 2, ... of this
+// thread; all loads are issued before the first LDS write so that one memory
+// latency covers the whole tile.
+template <typename T>
+__device__ __forceinline__ void m2l_stage(T (*X)[M2L_NT + 1], const int64_t *cbase, const double *MM, int64_t loff,
+                                          int xr, int xj) {
+#pragma unroll
+    for (int h = 0; h < M2L_NT / 2; h += 16) {
+        double v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int64_t b = cbase[xj + 2 * (h + i)];
+            v[i] = b >= 0 ? MM[b + loff] : 0.0;
         }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) X[xr][xj + 2 * (h + i)] = (T)v[i];
     }
 }
 
 // offset-major M2L for one right-hand side: one block per (offset, kind, column
 // tile); columns are (interaction-list entry q, channel).  Writes the per-entry
 // contribution YB[q][ch][NN] summed over the window's lags.
-template <typename T, int NT>
-__global__ void __launch_bounds__(256) k_m2l_off(const int *tile_code, const int *tile_kind, const int *tile_col0,
-                                                 const int *tile_ncol, const int *col_q, const int *col_ch,
-                                                 const int *il_src, const T *MM, int WR, int k, int W, double hs,
-                                                 double ht, double cl, T *YB) {
+template <typename T>
+__global__ void __launch_bounds__(M2L_THREADS) k_m2l_off(const int *tile_code, const int *tile_kind,
+                                                         const int *tile_col0, const int *tile_ncol, const int *col_q,
+                                                         const int *col_ch, const int *il_src, const double *MM, int WR,
+                                                         int k, int W, double hs, double ht, double cl, double *YB) {
     const int tile = blockIdx.x;
     const int code = tile_code[tile], kind = tile_kind[tile], col0 = tile_col0[tile], ncol = tile_ncol[tile];
     const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    __shared__ M2LTables tb;
-    __shared__ T X[NN][NT + 1];
-    m2l_tables(tb, hs, ht, cl, tid);
-    typename Mma<T>::acc_t acc[4][NT / 16];
-    for (int rb = 0; rb < 4; ++rb)
-        for (int cb = 0; cb < NT / 16; ++cb) acc[rb][cb] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    const int wr = wave & 3, wc = wave >> 2;
+    __shared__ T X[NN][M2L_NT + 1];
+    __shared__ T tab[KTAB];
+    __shared__ int64_t cbase[M2L_NT];
+    int base[4];
+    m2l_row_base(base, wr, lane);
+    const double gs = hs * (2.0 / (P - 1)), cgt = cl * ht * (2.0 / (P - 1));
+    typename Mma<T>::acc_t acc[4][2];
+    for (int rb = 0; rb < 4; ++rb) acc[rb][0] = acc[rb][1] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    // MM offset of every column at slot 0 (-1: padding column)
+    if (tid < M2L_NT) {
+        int64_t b = -1;
+        if (tid < ncol) b = ((int64_t)il_src[col_q[col0 + tid]] * WR * 2 * NCH + col_ch[col0 + tid]) * NN;
+        cbase[tid] = b;
+    }
+    const int xr = tid & (NN - 1), xj = tid >> 8;
     for (int lag = 1; lag <= W; ++lag) {
         int ks = k + 1 - lag;
         if (ks < 0) break;
-        int sl = ks % WR, tf = lag == W ? 1 : 0;
+        const int64_t loff = (int64_t)((ks % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + xr;
         __syncthreads();
-        for (int j = 0; j < NT; ++j) {
-            T v = 0;
-            if (j < ncol) {
-                int q = col_q[col0 + j], ch = col_ch[col0 + j];
-                int S = il_src[q];
-                v = MM[((((size_t)S * WR + sl) * 2 + tf) * NCH + ch) * NN + tid];
-            }
-            X[tid][j] = v;
-        }
+        m2l_stage<T>(X, cbase, MM, loff, xr, xj);
+        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, cgt, 2.0 * cl);
         __syncthreads();
-        m2l_apply<T, NT>(acc, X, tb, ox, oy, oz, lag, kind, 2.0 * cl, wave, lane);
+        m2l_apply<T>(acc, X, tab, base, wc, lane);
     }
     for (int rb = 0; rb < 4; ++rb)
-        for (int cb = 0; cb < NT / 16; ++cb) {
-            int j = 16 * cb + (lane & 15);
+        for (int cb = 0; cb < 2; ++cb) {
+            int j = 32 * wc + 16 * cb + (lane & 15);
             if (j >= ncol) continue;
             int q = col_q[col0 + j], ch = col_ch[col0 + j];
             for (int v = 0; v < 4; ++v) {
-                int row = 64 * wave + 16 * rb + Mma<T>::row(lane, v);
-                YB[((size_t)q * NCH + ch) * NN + row] = acc[rb][cb][v];
+                int row = 64 * wr + 16 * rb + Mma<T>::row(lane, v);
+                YB[((size_t)q * NCH + ch) * NN + row] = (double)acc[rb][cb][v];
             }
         }
 }
 
 // LC(O) = PEND(O, parity) + sum over O's interaction-list entries of YB (target-owned, fixed order)
-template <typename T>
-__global__ void k_m2l_reduce(int n, const int *il_off, const T *YB, const T *PEND, int parity, T *LC) {
+__global__ void k_m2l_reduce(int n, const int *il_off, const double *YB, const double *PEND, int parity, double *LC) {
     int O = blockIdx.x, c = blockIdx.y, v = threadIdx.x;
     double s = PEND[(((size_t)O * 2 + parity) * NCH + c) * NN + v];
     for (int q = il_off[O]; q < il_off[O + 1]; ++q) s += YB[((size_t)q * NCH + c) * NN + v];
-    LC[((size_t)O * NCH + c) * NN + v] = (T)s;
+    LC[((size_t)O * NCH + c) * NN + v] = s;
 }
 
 // target-major M2L for batched right-hand sides: one block per (target, kind,
-// (channel, rhs) tile of NT columns); items are (interaction-list source, lag).
-template <typename T, int NT>
-__global__ void __launch_bounds__(256) k_m2l_tgt(const int *il_off, const int *il_src, const int *il_code, const T *MM,
-                                                 int WR, int k, int W, double hs, double ht, double cl, const T *PEND,
-                                                 T *LC, int nrhs) {
+// (channel, rhs) tile of 64 columns); items are (interaction-list source, lag).
+template <typename T>
+__global__ void __launch_bounds__(M2L_THREADS) k_m2l_tgt(const int *il_off, const int *il_src, const int *il_code,
+                                                         const double *MM, int WR, int k, int W, double hs, double ht,
+                                                         double cl, const double *PEND, double *LC, int nrhs) {
     const int O = blockIdx.x, kind = blockIdx.y;
     const int c0 = kind == 0 ? 0 : 3, nc = kind == 0 ? 3 : 4;
     const int ncolt = nc * nrhs;
-    const int col0 = blockIdx.z * NT;
+    const int col0 = blockIdx.z * M2L_NT;
     if (col0 >= ncolt) return;
-    const int ncol = min(NT, ncolt - col0);
+    const int ncol = min(M2L_NT, ncolt - col0);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wr = wave & 3, wc = wave >> 2;
     const int parity = (k + 1) & 1;
-    __shared__ M2LTables tb;
-    __shared__ T X[NN][NT + 1];
-    m2l_tables(tb, hs, ht, cl, tid);
-    typename Mma<T>::acc_t acc[4][NT / 16];
-    for (int rb = 0; rb < 4; ++rb)
-        for (int cb = 0; cb < NT / 16; ++cb) acc[rb][cb] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    __shared__ T X[NN][M2L_NT + 1];
+    __shared__ T tab[KTAB];
+    __shared__ int64_t cbase[M2L_NT];
+    int base[4];
+    m2l_row_base(base, wr, lane);
+    const double gs = hs * (2.0 / (P - 1)), cgt = cl * ht * (2.0 / (P - 1));
+    typename Mma<T>::acc_t acc[4][2];
+    for (int rb = 0; rb < 4; ++rb) acc[rb][0] = acc[rb][1] = typename Mma<T>::acc_t{0, 0, 0, 0};
+    const int xr = tid & (NN - 1), xj = tid >> 8;
     for (int q = il_off[O]; q < il_off[O + 1]; ++q) {
         int S = il_src[q], code = il_code[q];
         int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
+        __syncthreads();
+        if (tid < M2L_NT) {
+            int64_t b = -1;
+            if (tid < ncol) {
+                int cc = (col0 + tid) / nrhs, r = (col0 + tid) % nrhs;
+                b = (((int64_t)S * WR * 2 * NCH + c0 + cc) * nrhs + r) * NN;
+            }
+            cbase[tid] = b;
+        }
         for (int lag = 1; lag <= W; ++lag) {
             int ks = k + 1 - lag;
             if (ks < 0) break;
-            int sl = ks % WR, tf = lag == W ? 1 : 0;
+            const int64_t loff = (int64_t)((ks % WR) * 2 + (lag == W ? 1 : 0)) * NCH * nrhs * NN + xr;
             __syncthreads();
-            for (int j = 0; j < NT; ++j) {
-                T v = 0;
-                if (j < ncol) {
-                    int cc = (col0 + j) / nrhs, r = (col0 + j) % nrhs;
-                    v = MM[((((size_t)S * WR + sl) * 2 + tf) * NCH + c0 + cc) * nrhs * NN + (size_t)r * NN + tid];
-                }
-                X[tid][j] = v;
-            }
+            m2l_stage<T>(X, cbase, MM, loff, xr, xj);
+            m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, cgt, 2.0 * cl);
             __syncthreads();
-            m2l_apply<T, NT>(acc, X, tb, ox, oy, oz, lag, kind, 2.0 * cl, wave, lane);
+            m2l_apply<T>(acc, X, tab, base, wc, lane);
         }
     }
     for (int rb = 0; rb < 4; ++rb)
-        for (int cb = 0; cb < NT / 16; ++cb) {
-            int j = 16 * cb + (lane & 15);
+        for (int cb = 0; cb < 2; ++cb) {
+            int j = 32 * wc + 16 * cb + (lane & 15);
             if (j >= ncol) continue;
             int cc = (col0 + j) / nrhs, r = (col0 + j) % nrhs;
             for (int v = 0; v < 4; ++v) {
-                int row = 64 * wave + 16 * rb + Mma<T>::row(lane, v);
+                int row = 64 * wr + 16 * rb + Mma<T>::row(lane, v);
                 size_t o = (((size_t)O * NCH + c0 + cc) * nrhs + r) * NN + row;
                 size_t pe = ((((size_t)O * 2 + parity) * NCH + c0 + cc) * nrhs + r) * NN + row;
-                LC[o] = (T)((double)acc[rb][cb][v] + (double)PEND[pe]);
+                LC[o] = (double)acc[rb][cb][v] + PEND[pe];
             }
         }
+}
+
+// launch of the M2L of one level at gate k
+template <typename T>
+static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
+    FarState *F = C->far;
+    const int nr = C->nrhs;
+    if (nr == 1) {
+        if (FL.ntile > 0)
+            hipLaunchKernelGGL(k_m2l_off<T>, dim3(FL.ntile), dim3(M2L_THREADS), 0, s, FL.tile_code, FL.tile_kind,
+                               FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, F->WR, k, F->W, FL.hs,
+                               FL.ht, C->c, FL.YB);
+        hipLaunchKernelGGL(k_m2l_reduce, dim3(FL.n, NCH), dim3(NN), 0, s, FL.n, FL.il_off, FL.YB, FL.PEND, (k + 1) & 1,
+                           FL.LC);
+    } else {
+        hipLaunchKernelGGL(k_m2l_tgt<T>, dim3(FL.n, 2, (4 * nr + M2L_NT - 1) / M2L_NT), dim3(M2L_THREADS), 0, s,
+                           FL.il_off, FL.il_src, FL.il_code, FL.MM, F->WR, k, F->W, FL.hs, FL.ht, C->c, FL.PEND, FL.LC, nr);
+    }
 }
 
 // L2L: PEND(child, h) = T_{oct,h}^T LC(parent) for the child's intervals 2(k+1)+h.
@@ -660,18 +719,7 @@ void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
         int k = alpha / FL.M - 1;
         {
             PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
-            if (nr == 1) {
-                if (FL.ntile > 0)
-                    hipLaunchKernelGGL((k_m2l_off<double, M2L_NT>), dim3(FL.ntile), dim3(256), 0, s, FL.tile_code,
-                                       FL.tile_kind, FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM,
-                                       F->WR, k, F->W, FL.hs, FL.ht, C->c, FL.YB);
-                hipLaunchKernelGGL((k_m2l_reduce<double>), dim3(FL.n, NCH), dim3(NN), 0, s, FL.n, FL.il_off, FL.YB,
-                                   FL.PEND, (k + 1) & 1, FL.LC);
-            } else {
-                hipLaunchKernelGGL((k_m2l_tgt<double, M2L_NT>), dim3(FL.n, 2, (4 * nr + M2L_NT - 1) / M2L_NT), dim3(256),
-                                   0, s, FL.il_off, FL.il_src, FL.il_code, FL.MM, F->WR, k, F->W, FL.hs, FL.ht, C->c,
-                                   FL.PEND, FL.LC, nr);
-            }
+            if (C->cfg.precision == TDBEM_FP64) m2l_launch<double>(C, FL, k, s); else m2l_launch<float>(C, FL, k, s);
         }
         if (FL.nparent > 0) {
             PhaseScope ps(C->prof, TDBEM_PH_L2L, s);

@@ -165,3 +165,84 @@ def test_batched_rhs_columns_equal_single_runs(setup):
             ref = J.cpu().numpy()
             assert np.abs(J3s[a - 1][r] - ref).max() <= 1e-10 * max(np.abs(ref).max(), 1e-30)
     B.close()
+
+
+# ------------------------------------------------------------ precision forms
+def _solver(dt, **kw):
+    v, f = icosphere(2)
+    return tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=LEAF, gmres_rtol=1e-13,
+                                           gmres_maxit=200, **kw))
+
+
+# The FP32 bound: the far field applies the undifferentiated kernels (U grows
+# like the square of the lag) to the third-difference moments, and for a random
+# history the window's terms cancel down to the retarded potential, so the FP32
+# rounding of each term is amplified by about (W M)^2 (here 10 * 3 intervals).
+@pytest.mark.parametrize("prec,tol", [(tdbem.FP32, 2e-3)])
+def test_precision_forms_potentials(setup, prec, tol):
+    """The FP32 form (FP32 near coefficients, FP32 operator and products on the
+    matrix cores, FP64 moments and sums) against near + all-interval far of the
+    oracles."""
+    torch = _torch()
+    m, S, F, Z, near, dt = setup
+    B = _solver(dt, precision=prec)
+    n_hist = 97
+    rng = np.random.default_rng(5)
+    hist = rng.standard_normal((n_hist, m.ne))
+    a = n_hist + 1
+    Zn = Z * near[:, :, None]
+    ref = F.far_history(hist)[a - 1]
+    for g in range(2, Z.shape[2]):
+        if 0 <= a - g < n_hist:
+            ref += Zn[:, :, g] @ hist[a - g]
+    out = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+    B.potentials(torch.tensor(hist, device="cuda"), n_hist, out)
+    rel = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
+    print(f"precision {prec}: rel err {rel:.2e}")
+    assert rel < tol
+    B.close()
+
+
+def test_fp32_form_batched_equals_single(setup):
+    """FP32 form: target-major batched M2L against offset-major single runs."""
+    torch = _torch()
+    m, S, F, Z, near, dt = setup
+    B = _solver(dt, precision=tdbem.FP32, n_rhs=2)
+    S1 = _solver(dt, precision=tdbem.FP32)
+    n_hist = 60
+    rng = np.random.default_rng(3)
+    hist = rng.standard_normal((n_hist, 2, m.ne))
+    out2 = torch.zeros((2, m.ne), dtype=torch.float64, device="cuda")
+    B.potentials(torch.tensor(hist, device="cuda"), n_hist, out2)
+    for r in range(2):
+        o1 = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+        S1.potentials(torch.tensor(np.ascontiguousarray(hist[:, r]), device="cuda"), n_hist, o1)
+        ref = o1.cpu().numpy()
+        rel = np.abs(out2[r].cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert rel < 2e-3, rel     # both sides carry the amplified FP32 rounding (see above)
+    B.close()
+    S1.close()
+
+
+def test_fp32_form_marched_current_close_to_fp64(setup):
+    """The FP32 form marches close to the FP64 run on the same incident field
+    (relative, max over steps and edges; 1.4e-4 measured: the amplified
+    rounding of the undifferentiated far kernels, not the near field)."""
+    torch = _torch()
+    m, S, F, Z, near, dt = setup
+    B = _solver(dt, precision=tdbem.FP32)
+    pulse = gaussian_pulse(150e6, 100e6)
+    S.reset()
+    V = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+    J64 = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+    J32 = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+    worst, jmax = 0.0, 0.0
+    for a in range(1, 150):
+        S.incident([pulse], a, V)
+        S.step(V, J64)
+        B.step(V, J32)
+        worst = max(worst, (J64 - J32).abs().max().item())
+        jmax = max(jmax, J64.abs().max().item())
+    print(f"FP32 form vs FP64: max |dJ| / max |J| = {worst / jmax:.2e}")
+    assert worst / jmax < 5e-4
+    B.close()
