@@ -24,8 +24,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MOT steps/s and M2L roofline %, chosen vs plain FP64 IFMM at rel err 1e-4"
 PEAK_HBM = 8.0e12          # B/s
-PEAK_FP64 = 78.6e12        # FLOP/s (vector and matrix)
-PEAK_FP32 = 157.3e12
+PEAK_FP64 = 78.6e12        # FLOP/s, dense FP64 on the matrix cores
+PEAK_FP32 = 157.3e12       # FLOP/s, dense FP32 on the matrix cores
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_m2l_off_sphere20480_traffic.json")
 
 
 def gate_schedule(Mt, lmax, first, last):
@@ -35,6 +36,35 @@ def gate_schedule(Mt, lmax, first, last):
         M = Mt[l]
         out[l] = [a for a in range(first, last + 1) if a % M == 0]
     return out
+
+
+def m2l_traffic(form):
+    """HBM bytes per M2L launch from the committed counter summary, or None when
+    the M2L source has changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        src = os.path.join(ROOT, rec["source"])
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if sha != rec["source_sha256"] or form not in rec["bytes_per_launch"]:
+            return None
+        return rec["bytes_per_launch"][form]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_probe(torch, mib=512):
+    """One plain device copy of known size (read mib MiB, write mib MiB): the
+    reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    n = mib * 1024 * 1024 // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    return {"bytes_read": n * 8, "bytes_written": n * 8}
 
 
 def cpu_baseline(workload, rows=8):
@@ -93,6 +123,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, run one 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
@@ -154,9 +186,11 @@ def main():
     t_m2l = ph["m2l"][0] * 1e-3
     t_near = ph["near"][0] * 1e-3
     if t_m2l > 0:
-        kernels["m2l"] = {"bound": "alu", "achieved": m2l_flops / t_m2l / 1e12, "unit": "TFLOP/s",
+        kernels["m2l"] = {"bound": "mfma", "achieved": m2l_flops / t_m2l / 1e12, "unit": "TFLOP/s",
                           "peak": (PEAK_FP64 if prec == tdbem.FP64 else PEAK_FP32) / 1e12,
-                          "launches": ph["m2l"][1], "ms_total": ph["m2l"][0]}
+                          "launches": ph["m2l"][1], "ms_total": ph["m2l"][0],
+                          "ms_per_launch": ph["m2l"][0] / max(ph["m2l"][1], 1),
+                          "flop_per_launch": m2l_flops / max(ph["m2l"][1], 1)}
     if t_near > 0:
         kernels["near"] = {"bound": "hbm", "achieved": near_bytes / t_near / 1e9, "unit": "GB/s",
                            "peak": PEAK_HBM / 1e9, "launches": ph["near"][1], "ms_total": ph["near"][0]}
@@ -164,8 +198,9 @@ def main():
     roof = None
     if dom:
         kd = kernels[dom]
+        traffic = m2l_traffic(args.form) if (dom == "m2l" and nr == 1) else None
         roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
-                "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"], "traffic": None}
+                "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"], "traffic": traffic}
     res = {
         "metric": METRIC,
         "value": K / el,
@@ -185,11 +220,14 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "phase_ms": {k: v[0] for k, v in ph.items()},
+        "phase_launches": {k: v[1] for k, v in ph.items()},
         "gmres_iters_mean": float(np.mean(iters)),
         "setup_s": setup_s,
         "hierarchy": {k: info[k] for k in ("lmax", "Mt", "ncells", "nilist", "near_nnz", "near_pairs", "z0_nnz", "window")},
         "device_gb": info["device_bytes"] / 1e9,
     }
+    if args.copy_probe:
+        res["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w)
     S.close()

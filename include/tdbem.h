@@ -139,10 +139,12 @@ enum {
 };
 
 /* Phases timed by tdbem_profile (HIP events on the work stream around each
- * phase's launches; GMRES time includes its host-side Givens updates). */
+ * phase's launches).  TDBEM_PH_M2L times the M2L product kernel alone (one
+ * launch per level and time gate); TDBEM_PH_M2L_SUM the per-target sum of its
+ * interaction-list contributions (one right-hand side only). */
 enum {
     TDBEM_PH_NEAR = 0, TDBEM_PH_GMRES = 1, TDBEM_PH_P2M = 2, TDBEM_PH_M2M = 3, TDBEM_PH_M2L = 4,
-    TDBEM_PH_L2L = 5, TDBEM_PH_L2P = 6, TDBEM_PH_OTHER = 7, TDBEM_NPHASE = 8
+    TDBEM_PH_L2L = 5, TDBEM_PH_L2P = 6, TDBEM_PH_OTHER = 7, TDBEM_PH_M2L_SUM = 8, TDBEM_NPHASE = 9
 };
 int tdbem_query(const tdbem_ctx *ctx, int32_t key, void *out);
 

@@ -598,13 +598,17 @@ static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
     FarState *F = C->far;
     const int nr = C->nrhs;
     if (nr == 1) {
-        if (FL.ntile > 0)
+        if (FL.ntile > 0) {
+            PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
             hipLaunchKernelGGL(k_m2l_off<T>, dim3(FL.ntile), dim3(M2L_THREADS), 0, s, FL.tile_code, FL.tile_kind,
                                FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, F->WR, k, F->W, FL.hs,
                                FL.ht, C->c, FL.YB);
+        }
+        PhaseScope ps(C->prof, TDBEM_PH_M2L_SUM, s);
         hipLaunchKernelGGL(k_m2l_reduce, dim3(FL.n, NCH), dim3(NN), 0, s, FL.n, FL.il_off, FL.YB, FL.PEND, (k + 1) & 1,
                            FL.LC);
     } else {
+        PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
         hipLaunchKernelGGL(k_m2l_tgt<T>, dim3(FL.n, 2, (4 * nr + M2L_NT - 1) / M2L_NT), dim3(M2L_THREADS), 0, s,
                            FL.il_off, FL.il_src, FL.il_code, FL.MM, F->WR, k, F->W, FL.hs, FL.ht, C->c, FL.PEND, FL.LC, nr);
     }
@@ -717,10 +721,7 @@ void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
         FarLevel &FL = F->lev[l];
         if (alpha % FL.M) continue;
         int k = alpha / FL.M - 1;
-        {
-            PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
-            if (C->cfg.precision == TDBEM_FP64) m2l_launch<double>(C, FL, k, s); else m2l_launch<float>(C, FL, k, s);
-        }
+        if (C->cfg.precision == TDBEM_FP64) m2l_launch<double>(C, FL, k, s); else m2l_launch<float>(C, FL, k, s);
         if (FL.nparent > 0) {
             PhaseScope ps(C->prof, TDBEM_PH_L2L, s);
             FarLevel &CL = F->lev[l + 1];

@@ -23,7 +23,7 @@ FP64, FP32, BF16 = 0, 1, 2
 GUESS_EXTRAP, GUESS_LEARNED = 0, 1
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
     Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT = range(17)
-PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other"]
+PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
            "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_destroy", "tdbem_last_error"]
