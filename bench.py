@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--guess", default="extrap", choices=["extrap", "learned"],
+                    help="initial guess of the Z0 solve (learned: the committed network parameters)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -141,9 +143,13 @@ def main():
     nr = len(w.pulses)
     prec = tdbem.FP64 if args.form == "fp64" else tdbem.FP32
     cfg = tdbem.Config(dt=w.dt, nt=w.nt, theta=w.theta, zeta=w.zeta, leaf_max=w.leaf_max, mode=tdbem.MODE_IFMM,
-                       precision=prec, n_rhs=nr, gmres_rtol=args.rtol, gmres_maxit=60)
+                       precision=prec, n_rhs=nr, gmres_rtol=args.rtol, gmres_maxit=60,
+                       guess=tdbem.GUESS_LEARNED if args.guess == "learned" else tdbem.GUESS_EXTRAP)
     t0 = time.perf_counter()
     S = tdbem.Solver(w.verts, w.tris, cfg)
+    if args.guess == "learned":
+        from paper_2303_05006_amd.train_guess import DEFAULT_OUT
+        S.guess_weights(np.load(DEFAULT_OUT))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     info = S.info()
@@ -216,7 +222,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{name}: PEC sphere r=1 m, 20480 triangles / {ne} RWG edges, c dt = 0.02 m, "
                                f"IFMM p_s=p_t=4, leaves <= 64 edges, {nr} incident field(s), steps {W + 1}..{last} of 1000",
-                   "form": args.form, "n_rhs": nr, "gmres_rtol": args.rtol},
+                   "form": args.form, "n_rhs": nr, "gmres_rtol": args.rtol, "guess": args.guess},
         "roofline": roof,
         "kernels": kernels,
         "phase_ms": {k: v[0] for k, v in ph.items()},

@@ -158,6 +158,41 @@ int tdbem_near_rows(tdbem_ctx *ctx, const int32_t *rows, int32_t n, int32_t G, d
  * the stream and folds the recorded event pairs into the totals. */
 int tdbem_profile(tdbem_ctx *ctx, int32_t enable);
 
+/* Learned initial guess of the Z0 solve (not part of the paper's method: an
+ * alternative to starting the solve of Eq. solve from the quadratic
+ * extrapolation 3J^{a-2} - 3J^{a-3} + J^{a-4}).  Per edge i and right-hand side,
+ * 116 features are formed:
+ *   f = 8e + s - 1 (e = 0..12, s = 1..8): sigma_ie J_e^{alpha-1-s}
+ *   f = 104 + e    (e = 0..11):           sigma_ie (R_e^{alpha-1} - (Z0 x)_e) / Z0_ee
+ * with e = 0 the edge itself and e = 1..12 its 12 nearest edges by midpoint
+ * distance (ties by canonical index), sigma_ie the sign of the dot product of
+ * the two edges' T+ -> T- centroid directions, R the step's right-hand side
+ * (V minus the near and far history) and x the extrapolation.  The features are divided by their
+ * largest magnitude s_i (1 if all vanish) and rounded to bf16 (x).  With
+ *   o(x) = relu(relu(x W1 + b1) W2 + b2) . w3 + b3
+ * (W1, W2 and the hidden layer rounded to bf16, FP32 accumulation) the guess is
+ *   J_guess = extrapolation + s_i (o(x) - o(-x)) / 2.
+ * The solve itself stays FP64 and converges to the same tolerance from either
+ * guess. */
+#define TDBEM_GUESS_NFEAT 116
+#define TDBEM_GUESS_NHIDDEN 128
+#define TDBEM_GUESS_NPARAMS (116 * 128 + 128 + 128 * 128 + 128 + 128 + 1)
+
+/* Load the network: params host FP32 [TDBEM_GUESS_NPARAMS] in the order
+ * W1 [116][128] (feature, hidden unit), b1 [128], W2 [128][128] (input unit,
+ * output unit), b2 [128], w3 [128], b3.  Copied; EINVAL if n_params differs or a
+ * value is not finite.  Steps of a context configured with
+ * guess = TDBEM_GUESS_LEARNED fail with EINVAL until parameters are loaded. */
+int tdbem_guess_weights(tdbem_ctx *ctx, const float *params, int64_t n_params);
+
+/* Capture the guess inputs of the following steps (training data): before each
+ * solve, features_dev (device FP32 [n_rhs][N_e][116], canonical edge order)
+ * receives the normalised features x and aux_dev (device FP64 [n_rhs][N_e][2])
+ * the scale s_i and the extrapolation.  The buffers are overwritten by every
+ * step until capture is switched off with two null pointers; the caller owns
+ * them and keeps them alive meanwhile. */
+int tdbem_guess_capture(tdbem_ctx *ctx, float *features_dev, double *aux_dev);
+
 void tdbem_destroy(tdbem_ctx *ctx);
 const char *tdbem_last_error(void);
 

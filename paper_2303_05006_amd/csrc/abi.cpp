@@ -69,23 +69,6 @@ size_t gmres_work_doubles(const tdbem_ctx *C, int maxit);
 bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s);
 size_t gmres_coop_work_doubles(int ne);
 
-template <typename T>
-static T *dalloc(tdbem_ctx *C, size_t n) {
-    if (n == 0) n = 1;
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(T));
-    if (e != hipSuccess) throw Error{TDBEM_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
-    C->allocs.push_back(p);
-    C->dev_bytes += n * sizeof(T);
-    return (T *)p;
-}
-template <typename T>
-static T *dupload(tdbem_ctx *C, const std::vector<T> &v) {
-    T *p = dalloc<T>(C, v.size());
-    if (!v.empty()) TD_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return p;
-}
-
 static GeoDev geo(const tdbem_ctx *C) {
     return GeoDev{C->d_xyz, C->d_tri, C->d_area, C->d_nrm, C->d_qpt, C->d_etri, C->d_efree, C->d_elen,
                   C->cdt, C->cfg.dt, C->cfg.eps, C->cfg.mu, C->cfg.theta, C->cfg.zeta, C->eta};
@@ -283,6 +266,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->hp_nnz = nnz;
     // ---- far field
     if (cfg->mode == TDBEM_MODE_IFMM) ifmm_setup(C);
+    guess_setup(C);
     // ---- march state
     int R = 8;
     int need = std::max(maxlag + 2, C->far_ring_need);
@@ -326,6 +310,7 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
             launch_axpby(nv, -1.0, C->d_tmp, 1.0, C->d_rhs, s);
             if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_subtract_far(C, a, C->d_rhs, s);
             launch_extrap(C, a, C->d_x, s);
+            if (guess_active(C)) launch_guess(C, a, s);
         }
         bool ok = true;
         {
@@ -501,9 +486,22 @@ int tdbem_profile(tdbem_ctx *C, int32_t enable) {
     return TDBEM_OK;
 }
 
+int tdbem_guess_weights(tdbem_ctx *C, const float *params, int64_t n) {
+    if (!C || !params) { set_error("null argument"); return TDBEM_EINVAL; }
+    TD_GUARD({ guess_load(C, params, n); });
+    return TDBEM_OK;
+}
+
+int tdbem_guess_capture(tdbem_ctx *C, float *feat, double *aux) {
+    if (!C) { set_error("null argument"); return TDBEM_EINVAL; }
+    TD_GUARD({ guess_capture(C, feat, aux); });
+    return TDBEM_OK;
+}
+
 void tdbem_destroy(tdbem_ctx *C) {
     if (!C) return;
     ifmm_destroy(C);
+    guess_destroy(C);
     for (void *p : C->allocs) (void)hipFree(p);
     if (C->h_scal) (void)hipHostFree(C->h_scal);
     if (C->h_iflag) (void)hipHostFree(C->h_iflag);

@@ -283,6 +283,11 @@ void launch_ring_put(const tdbem_ctx *C, int slot, const double *x, hipStream_t 
     hipLaunchKernelGGL(k_ring_put, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, slot, x, C->d_Jring);
     TD_HIP(hipGetLastError());
 }
+void launch_spmv(const tdbem_ctx *C, const double *x, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmv, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->d_z0_ptr,
+                       C->d_z0_col, C->d_z0_val, x, y);
+    TD_HIP(hipGetLastError());
+}
 void launch_extrap(const tdbem_ctx *C, int alpha, double *x, hipStream_t s) {
     hipLaunchKernelGGL(k_extrap, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, alpha, C->d_Jring, x);
     TD_HIP(hipGetLastError());

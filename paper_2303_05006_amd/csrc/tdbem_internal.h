@@ -78,7 +78,8 @@ struct GeoDev {
     double cdt, dt, eps, mu, theta, zeta, eta;
 };
 
-struct FarState;  // IFMM device state (ifmm.hip)
+struct FarState;
+struct GuessState;  // learned-guess device state (guess.hip)
 
 // per-phase timing with HIP event pairs recorded on the work stream
 struct Profiler {
@@ -168,5 +169,36 @@ struct tdbem_ctx {
     int window = 0;                 // source intervals per M2L (mu + 1)
     int far_ring_need = 0;          // history ring length the far field needs
     tdbem::FarState *far = nullptr;
+    tdbem::GuessState *guess = nullptr;   // learned initial guess (features, network)
     tdbem::Profiler prof;
 };
+
+namespace tdbem {
+
+// device allocations owned by the context (freed in tdbem_destroy)
+template <typename T>
+inline T *dalloc(tdbem_ctx *C, size_t n) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw Error{TDBEM_ENOMEM, "hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+    C->allocs.push_back(p);
+    C->dev_bytes += n * sizeof(T);
+    return (T *)p;
+}
+template <typename T>
+inline T *dupload(tdbem_ctx *C, const std::vector<T> &v) {
+    T *p = dalloc<T>(C, v.size());
+    if (!v.empty()) TD_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+}
+
+void guess_setup(tdbem_ctx *C);
+void guess_destroy(tdbem_ctx *C);
+void guess_load(tdbem_ctx *C, const float *params, int64_t n);
+void guess_capture(tdbem_ctx *C, float *feat, double *aux);
+bool guess_active(const tdbem_ctx *C);
+void launch_guess(tdbem_ctx *C, int alpha, hipStream_t s);
+void launch_spmv(const tdbem_ctx *C, const double *x, double *y, hipStream_t s);
+
+}  // namespace tdbem

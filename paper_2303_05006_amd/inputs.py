@@ -190,6 +190,24 @@ def gaussian_pulse(f0, fbw, k=(0, 0, 1), p=(1, 0, 0), E0=1.0, r_max=1.0):
                  delay=5.0 * sigma + r_max / C0, kind="gauss")
 
 
+def random_pulses(n: int, seed: int, f0_range=(50e6, 150e6), r_max=1.0):
+    """n modulated Gaussian pulses with seeded random direction (uniform on the
+    sphere), polarisation angle psi ~ U[0, 2 pi), centre frequency f0 uniform in
+    f0_range and bandwidth 2/3 f0."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        k = rng.standard_normal(3)
+        k /= np.linalg.norm(k)
+        a = np.array([1.0, 0.0, 0.0]) if abs(k[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+        e1 = a - k * (a @ k); e1 /= np.linalg.norm(e1)
+        e2 = np.cross(k, e1)
+        psi = rng.uniform(0.0, 2.0 * math.pi)
+        f0 = rng.uniform(*f0_range)
+        out.append(gaussian_pulse(f0, 2.0 * f0 / 3.0, k=k, p=math.cos(psi) * e1 + math.sin(psi) * e2, r_max=r_max))
+    return out
+
+
 def fibonacci_directions(n: int, seed: int = 2303):
     """n incidence directions on a Fibonacci sphere with seeded uniform random
     polarisation angles psi ~ U[0, 2 pi).  Returns (k[n,3], p[n,3])."""

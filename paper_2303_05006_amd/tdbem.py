@@ -26,7 +26,10 @@ Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NIL
 PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
-           "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_destroy", "tdbem_last_error"]
+           "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_guess_weights", "tdbem_guess_capture",
+           "tdbem_destroy", "tdbem_last_error"]
+GUESS_NFEAT, GUESS_NHIDDEN = 116, 128
+GUESS_NPARAMS = 116 * 128 + 128 + 128 * 128 + 128 + 128 + 1
 
 
 class TdbemError(RuntimeError):
@@ -67,6 +70,8 @@ def load():
         L.tdbem_query.argtypes = [P, i32, P]
         L.tdbem_near_rows.argtypes = [P, P, i32, i32, P]
         L.tdbem_profile.argtypes = [P, i32]
+        L.tdbem_guess_weights.argtypes = [P, P, i64]
+        L.tdbem_guess_capture.argtypes = [P, P, P]
         L.tdbem_destroy.argtypes = [P]
         L.tdbem_destroy.restype = None
         L.tdbem_last_error.restype = ctypes.c_char_p
@@ -195,6 +200,18 @@ class Solver:
         ms = self.query_array(Q_PHASE_MS, len(PHASES), np.float64)
         cnt = self.query_array(Q_PHASE_COUNT, len(PHASES), np.int64)
         return {p: (float(ms[i]), int(cnt[i])) for i, p in enumerate(PHASES)}
+
+    def guess_weights(self, params):
+        """Load the learned-guess network (FP32, GUESS_NPARAMS values in the
+        order W1 [116][128], b1, W2 [128][128], b2, w3, b3)."""
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        _check(load().tdbem_guess_weights(self._h, p.ctypes.data_as(ctypes.c_void_p), p.size))
+
+    def guess_capture(self, features=None, aux=None):
+        """Capture the guess inputs of the following steps into device tensors
+        features [n_rhs][N_e][116] float32 and aux [n_rhs][N_e][2] float64
+        (scale, extrapolation); no arguments switches capture off."""
+        _check(load().tdbem_guess_capture(self._h, _ptr(features), _ptr(aux)))
 
     def gmres_iters(self):
         return self.query_i32(Q_GMRES_ITERS)
