@@ -193,6 +193,27 @@ int tdbem_guess_weights(tdbem_ctx *ctx, const float *params, int64_t n_params);
  * them and keeps them alive meanwhile. */
 int tdbem_guess_capture(tdbem_ctx *ctx, float *features_dev, double *aux_dev);
 
+/* Training of the guess network (FP32, no context needed).  Gradient of the
+ * loss L = (1/n) sum_s (g(x_s) - y_s)^2 with g the odd network above evaluated
+ * in FP32 without the bf16 roundings of inference:
+ *   params_dev FP32 [TDBEM_GUESS_NPARAMS] (order of tdbem_guess_weights),
+ *   X_dev FP32 [n][116] features, Y_dev FP32 [n] targets (the correction
+ *   (J - extrapolation) / s of captured steps),
+ *   grad_dev FP32 [TDBEM_GUESS_NPARAMS] receives dL/dparams (overwritten),
+ *   loss_dev FP32 [1] receives L (overwritten).
+ * All pointers are device memory owned by the caller; the work is issued on
+ * stream (a hipStream_t; null for the default stream) and not waited for.
+ * Gradient sums use atomic additions, so their rounding order varies. */
+int tdbem_guess_grad(const float *params_dev, const float *X_dev, const float *Y_dev, int64_t n,
+                     float *grad_dev, float *loss_dev, void *stream);
+
+/* One Adam step in place on params_dev with moments m_dev, v_dev (device FP32
+ * [TDBEM_GUESS_NPARAMS], zero before the first step) and step count t >= 1:
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   params -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+int tdbem_guess_adam(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, int32_t t,
+                     float lr, float beta1, float beta2, float eps, void *stream);
+
 void tdbem_destroy(tdbem_ctx *ctx);
 const char *tdbem_last_error(void);
 

@@ -498,6 +498,17 @@ int tdbem_guess_capture(tdbem_ctx *C, float *feat, double *aux) {
     return TDBEM_OK;
 }
 
+int tdbem_guess_grad(const float *P, const float *X, const float *Y, int64_t n, float *G, float *loss, void *stream) {
+    TD_GUARD({ guess_grad(P, X, Y, n, G, loss, (hipStream_t)stream); });
+    return TDBEM_OK;
+}
+
+int tdbem_guess_adam(float *P, const float *G, float *M, float *V, int32_t t, float lr, float b1, float b2, float eps,
+                     void *stream) {
+    TD_GUARD({ guess_adam(P, G, M, V, t, lr, b1, b2, eps, (hipStream_t)stream); });
+    return TDBEM_OK;
+}
+
 void tdbem_destroy(tdbem_ctx *C) {
     if (!C) return;
     ifmm_destroy(C);

@@ -27,6 +27,7 @@ PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
            "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_guess_weights", "tdbem_guess_capture",
+           "tdbem_guess_grad", "tdbem_guess_adam",
            "tdbem_destroy", "tdbem_last_error"]
 GUESS_NFEAT, GUESS_NHIDDEN = 116, 128
 GUESS_NPARAMS = 116 * 128 + 128 + 128 * 128 + 128 + 128 + 1
@@ -72,6 +73,9 @@ def load():
         L.tdbem_profile.argtypes = [P, i32]
         L.tdbem_guess_weights.argtypes = [P, P, i64]
         L.tdbem_guess_capture.argtypes = [P, P, P]
+        f32 = ctypes.c_float
+        L.tdbem_guess_grad.argtypes = [P, P, P, i64, P, P, P]
+        L.tdbem_guess_adam.argtypes = [P, P, P, P, i32, f32, f32, f32, f32, P]
         L.tdbem_destroy.argtypes = [P]
         L.tdbem_destroy.restype = None
         L.tdbem_last_error.restype = ctypes.c_char_p
@@ -109,6 +113,22 @@ class Config:
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def guess_grad(params, X, Y, grad, loss, stream=None):
+    """Loss gradient of the guess network on a batch (device FP32 tensors)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().tdbem_guess_grad(_ptr(params), _ptr(X), _ptr(Y), int(X.shape[0]), _ptr(grad), _ptr(loss),
+                                   ctypes.c_void_p(s.cuda_stream)))
+
+
+def guess_adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One Adam step in place on the guess parameters (device FP32 tensors)."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().tdbem_guess_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(t), lr, beta1, beta2, eps,
+                                   ctypes.c_void_p(s.cuda_stream)))
 
 
 class Solver:

@@ -5,14 +5,16 @@ Training data come from the library itself: marching runs with feature capture
 switched on record, for every step and edge, the normalised features x, the
 scale s and the extrapolation; the target is the solved current, as the
 correction y = (J - extrapolation) / s.  The odd network g(x) = (o(x) - o(-x)) / 2
-is fitted to y by Adam in FP32 (torch on the GPU); the library rounds W1 and W2
-to bf16 when the parameters are loaded.
+is fitted to y by Adam in FP32 with the library's own training kernels
+(tdbem_guess_grad, tdbem_guess_adam; torch only holds the buffers); the library
+rounds W1 and W2 to bf16 when the parameters are loaded for inference.
 
 python -m paper_2303_05006_amd.train_guess [--runs 24] [--rhs 8] [--nt 1000] [--out FILE]
 """
 from __future__ import annotations
 
 import argparse
+import math
 import os
 import sys
 import time
@@ -50,59 +52,46 @@ def collect(S, pulses, nt, first, frac, gen, torch):
     return torch.cat(xs), torch.cat(ys)
 
 
-class Odd:
-    """o(x) = relu(relu(x W1 + b1) W2 + b2) . w3 + b3; g(x) = (o(x) - o(-x)) / 2."""
-
-    def __init__(self, torch, seed):
-        from . import tdbem
-        g = torch.Generator(device="cuda").manual_seed(seed)
-        nf, nh = tdbem.GUESS_NFEAT, tdbem.GUESS_NHIDDEN
-
-        def init(*shape, fan_in):
-            return (torch.randn(*shape, device="cuda", generator=g) * (2.0 / fan_in) ** 0.5).requires_grad_()
-        self.W1 = init(nf, nh, fan_in=nf)
-        self.b1 = torch.zeros(nh, device="cuda", requires_grad=True)
-        self.W2 = init(nh, nh, fan_in=nh)
-        self.b2 = torch.zeros(nh, device="cuda", requires_grad=True)
-        self.w3 = torch.zeros(nh, device="cuda", requires_grad=True)     # starts at the extrapolation
-        self.b3 = torch.zeros(1, device="cuda", requires_grad=True)
-        self.params = [self.W1, self.b1, self.W2, self.b2, self.w3, self.b3]
-        self.torch = torch
-
-    def o(self, x):
-        F = self.torch.nn.functional
-        h = F.relu(x @ self.W1 + self.b1)
-        h = F.relu(h @ self.W2 + self.b2)
-        return h @ self.w3 + self.b3
-
-    def __call__(self, x):
-        return 0.5 * (self.o(x) - self.o(-x))
-
-    def flat(self):
-        return np.concatenate([p.detach().float().cpu().numpy().ravel() for p in self.params]).astype(np.float32)
+def init_params(seed):
+    """He-initialised W1, W2, zero biases and a zero last layer (so that the
+    untrained network reproduces the extrapolation)."""
+    from . import tdbem
+    rng = np.random.default_rng(seed)
+    nf, nh = tdbem.GUESS_NFEAT, tdbem.GUESS_NHIDDEN
+    p = np.concatenate([rng.standard_normal(nf * nh) * np.sqrt(2.0 / nf), np.zeros(nh),
+                        rng.standard_normal(nh * nh) * np.sqrt(2.0 / nh), np.zeros(nh), np.zeros(nh), [0.0]])
+    return p.astype(np.float32)
 
 
 def train(X, Y, torch, epochs=4, batch=8192, lr=1e-3, seed=0, log=print):
-    net = Odd(torch, seed)
-    opt = torch.optim.Adam(net.params, lr=lr)
+    """Adam with a cosine learning-rate schedule; gradients and updates run in
+    the library's training kernels (torch only holds the buffers)."""
+    from . import tdbem
+    P = torch.tensor(init_params(seed), device="cuda")
+    G = torch.zeros_like(P)
+    M = torch.zeros_like(P)
+    V = torch.zeros_like(P)
+    L = torch.zeros(1, dtype=torch.float32, device="cuda")
     n = X.shape[0]
     g = torch.Generator(device="cuda").manual_seed(seed + 1)
     var = float(Y.var())
-    steps = epochs * ((n + batch - 1) // batch)
-    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps)
+    nb = (n + batch - 1) // batch
+    total = epochs * nb
+    t = 0
     for ep in range(epochs):
         perm = torch.randperm(n, device="cuda", generator=g)
-        tot = 0.0
+        tot = torch.zeros(1, dtype=torch.float64, device="cuda")
         for b0 in range(0, n, batch):
             idx = perm[b0:b0 + batch]
-            loss = ((net(X[idx]) - Y[idx]) ** 2).mean()
-            opt.zero_grad()
-            loss.backward()
-            opt.step()
-            sched.step()
-            tot += float(loss) * len(idx)
-        log(f"epoch {ep}: mse {tot / n:.3e} (target variance {var:.3e})")
-    return net.flat()
+            Xb = X[idx].contiguous()
+            Yb = Y[idx].contiguous()
+            tdbem.guess_grad(P, Xb, Yb, G, L)
+            t += 1
+            rate = lr * 0.5 * (1.0 + math.cos(math.pi * (t - 1) / total))
+            tdbem.guess_adam(P, G, M, V, t, lr=rate)
+            tot += L.double() * len(idx)
+        log(f"epoch {ep}: mse {float(tot) / n:.3e} (target variance {var:.3e})")
+    return P.cpu().numpy()
 
 
 def main():

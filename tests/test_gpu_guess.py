@@ -6,6 +6,7 @@
 * the network's output equals an FP64 forward pass with the same bf16
   rounding of the matrix-core inputs;
 * zero parameters reproduce the extrapolation exactly;
+* the training kernels (loss gradient, Adam step) equal the FP64 oracle;
 * the trained parameters do not need more GMRES iterations than the
   extrapolation on a held-out body and held-out pulses.
 """
@@ -17,6 +18,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 from oracle import oracle as O
+from oracle import guess_mlp as GM
 from paper_2303_05006_amd import tdbem
 from paper_2303_05006_amd.inputs import icosphere, ellipsoid, gaussian_pulse, random_pulses, C0
 
@@ -192,6 +194,56 @@ def test_network_output_matches_fp64_forward(marched, zero):
     S.close()
     print(f"network output vs FP64 forward: {worst:.2e}")
     assert worst < 2e-3
+
+
+def _random_params(rng):
+    return GM.pack(rng.standard_normal((116, 128)) * np.sqrt(2 / 116), rng.standard_normal(128) * 0.3,
+                   rng.standard_normal((128, 128)) * np.sqrt(2 / 128), rng.standard_normal(128) * 0.3,
+                   rng.standard_normal(128) / np.sqrt(128), 0.2).astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 31, 100, 4099])
+def test_training_gradient_matches_oracle(n):
+    """n spans one partial block, several blocks and a ragged tail."""
+    torch = _torch()
+    rng = np.random.default_rng(n)
+    p = _random_params(rng)
+    x = (rng.standard_normal((n, 116)) * 0.5).astype(np.float32)
+    y = (rng.standard_normal(n) * 0.1).astype(np.float32)
+    P, X, Y = (torch.tensor(a, device="cuda") for a in (p, x, y))
+    G = torch.full((GM.NPARAMS,), 7.0, dtype=torch.float32, device="cuda")
+    L = torch.full((1,), 7.0, dtype=torch.float32, device="cuda")
+    tdbem.guess_grad(P, X, Y, G, L)
+    torch.cuda.synchronize()
+    g_ref = GM.grad(p.astype(np.float64), x.astype(np.float64), y.astype(np.float64))
+    l_ref = GM.loss(p.astype(np.float64), x.astype(np.float64), y.astype(np.float64))
+    g = G.cpu().numpy().astype(np.float64)
+    offs = np.cumsum([0, 116 * 128, 128, 128 * 128, 128, 128, 1])
+    for name, a, b in zip(["W1", "b1", "W2", "b2", "w3", "b3"], offs[:-1], offs[1:]):
+        scale = max(np.abs(g_ref[a:b]).max(), 1e-30)
+        err = np.abs(g[a:b] - g_ref[a:b]).max() / scale
+        print(f"n={n} {name}: {err:.2e}")
+        assert err < 1e-4 if name != "b3" else np.all(g[a:b] == 0.0)
+    assert abs(float(L.item()) - l_ref) <= 1e-5 * l_ref
+
+
+def test_adam_step_matches_oracle():
+    torch = _torch()
+    rng = np.random.default_rng(9)
+    p = rng.standard_normal(GM.NPARAMS).astype(np.float32)
+    g = rng.standard_normal(GM.NPARAMS).astype(np.float32)
+    m = (rng.standard_normal(GM.NPARAMS) * 0.1).astype(np.float32)
+    v = (rng.random(GM.NPARAMS) * 0.01).astype(np.float32)
+    P, G, Mt, Vt = (torch.tensor(a, device="cuda") for a in (p, g, m, v))
+    tdbem.guess_adam(P, G, Mt, Vt, 5, lr=1e-3)
+    torch.cuda.synchronize()
+    # the kernel takes its hyperparameters in FP32: give the oracle the same values
+    f32 = lambda z: float(np.float32(z))
+    q, m2, v2 = GM.adam(p.astype(np.float64), g.astype(np.float64), m.astype(np.float64), v.astype(np.float64), 5,
+                        lr=f32(1e-3), b1=f32(0.9), b2=f32(0.999), eps=f32(1e-8))
+    assert np.allclose(Mt.cpu().numpy(), m2, rtol=1e-5, atol=1e-7)
+    assert np.allclose(Vt.cpu().numpy(), v2, rtol=1e-5, atol=1e-9)
+    assert np.abs(P.cpu().numpy() - q).max() <= 1e-5 * 1e-3 + 1e-6 * np.abs(q).max()
 
 
 def test_trained_guess_does_not_cost_iterations():
