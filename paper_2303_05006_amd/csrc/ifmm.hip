@@ -116,7 +116,25 @@ void ifmm_setup(tdbem_ctx *C) {
     F->lmax = T.lmax;
     F->nrhs = C->nrhs;
     const double ds_max = T.side / std::ldexp(1.0, T.lmax);
-    int Mmax = (int)std::floor(ds_max / C->cdt);
+    double reach = ds_max;
+    if (const char *g = getenv("TDBEM_CAUSAL_GUARD"); g && atoi(g) == 1) {
+        // shrink the interval so that no far pair (cells one cell apart, supports
+        // reaching beyond their cell by up to delta) interacts within one interval
+        const HostMesh &Hm = C->H;
+        double delta = 0.0;
+        for (int e = 0; e < C->ne; ++e) {
+            const double *a = &Hm.xyz[3 * Hm.edge_v[2 * e]], *b = &Hm.xyz[3 * Hm.edge_v[2 * e + 1]];
+            double m[3] = {0.5 * (a[0] + b[0]), 0.5 * (a[1] + b[1]), 0.5 * (a[2] + b[2])};
+            for (int sd = 0; sd < 2; ++sd) {
+                const double *o = &Hm.xyz[3 * Hm.efree[2 * e + sd]];
+                delta = std::max(delta, std::sqrt((o[0] - m[0]) * (o[0] - m[0]) + (o[1] - m[1]) * (o[1] - m[1]) +
+                                                  (o[2] - m[2]) * (o[2] - m[2])));
+            }
+            delta = std::max(delta, 0.5 * Hm.elen[e]);
+        }
+        reach = ds_max - 2.0 * delta;
+    }
+    int Mmax = (int)std::floor(reach / C->cdt);
     TD_REQUIRE(Mmax >= 3, TDBEM_EBREAKDOWN,
                "time hierarchy breaks down: floor(d_s/(c dt)) = " + std::to_string(Mmax) + " < 3 steps per finest interval");
     double rho = C->cdt * Mmax / ds_max;
