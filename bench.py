@@ -114,6 +114,78 @@ def cpu_baseline(workload, rows=8):
                        f"untimed), {reps} repetitions, scaled by {m.ne}/{rows} rows")}
 
 
+def make_solver(torch, tdbem, w, form, guess, rtol):
+    nr = len(w.pulses)
+    prec = tdbem.FP64 if form == "fp64" else tdbem.FP32
+    cfg = tdbem.Config(dt=w.dt, nt=w.nt, theta=w.theta, zeta=w.zeta, leaf_max=w.leaf_max, mode=tdbem.MODE_IFMM,
+                       precision=prec, n_rhs=nr, gmres_rtol=rtol, gmres_maxit=60,
+                       guess=tdbem.GUESS_LEARNED if guess == "learned" else tdbem.GUESS_EXTRAP)
+    t0 = time.perf_counter()
+    S = tdbem.Solver(w.verts, w.tris, cfg)
+    if guess == "learned":
+        from paper_2303_05006_amd.train_guess import DEFAULT_OUT
+        S.guess_weights(np.load(DEFAULT_OUT))
+    torch.cuda.synchronize()
+    return S, time.perf_counter() - t0
+
+
+def march(torch, S, V, W, K, traj):
+    """W untimed + K timed steps on the resident incident fields V [W+K][rhs][N_e];
+    traj (or None) receives J of every step.  Returns (seconds, GMRES iterations)."""
+    J = torch.zeros(V.shape[1:], dtype=torch.float64, device="cuda")
+    for a in range(1, W + 1):
+        S.step(V[a - 1], J)
+        if traj is not None:
+            traj[a - 1].copy_(J)
+    torch.cuda.synchronize()
+    S.profile(True)
+    iters = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for a in range(W + 1, W + K + 1):
+        S.step(V[a - 1], J)
+        if traj is not None:
+            traj[a - 1].copy_(J)
+        iters.append(S.gmres_iters())
+    torch.cuda.synchronize()
+    return time.perf_counter() - t1, iters
+
+
+def kernel_rooflines(info, ph, W, K, nr, prec_fp64, form):
+    """Achieved rates of the M2L and near-field kernels over the timed steps."""
+    lmax = info["lmax"]
+    gates = gate_schedule(info["Mt"], lmax, W + 1, W + K)
+    win = info["window"]
+    m2l_flops = 0.0
+    for l in range(2, lmax + 1):
+        for a in gates[l]:
+            k = a // info["Mt"][l] - 1
+            lags = min(win, k + 1)
+            m2l_flops += info["nilist"][l] * lags * 7 * 2.0 * 256 * 256 * nr
+    vb = 8 if prec_fp64 else 4
+    near_bytes = K * (info["near_nnz"] * vb + info["near_pairs"] * 8 + info["ne"] * 8 * nr)
+    kernels = {}
+    t_m2l = ph["m2l"][0] * 1e-3
+    t_near = ph["near"][0] * 1e-3
+    if t_m2l > 0:
+        kernels["m2l"] = {"bound": "mfma", "achieved": m2l_flops / t_m2l / 1e12, "unit": "TFLOP/s",
+                          "peak": (PEAK_FP64 if prec_fp64 else PEAK_FP32) / 1e12,
+                          "launches": ph["m2l"][1], "ms_total": ph["m2l"][0],
+                          "ms_per_launch": ph["m2l"][0] / max(ph["m2l"][1], 1),
+                          "flop_per_launch": m2l_flops / max(ph["m2l"][1], 1)}
+    if t_near > 0:
+        kernels["near"] = {"bound": "hbm", "achieved": near_bytes / t_near / 1e9, "unit": "GB/s",
+                           "peak": PEAK_HBM / 1e9, "launches": ph["near"][1], "ms_total": ph["near"][0]}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
+    roof = None
+    if dom:
+        kd = kernels[dom]
+        traffic = m2l_traffic(form) if (dom == "m2l" and nr == 1) else None
+        roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
+                "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"], "traffic": traffic}
+    return roof, kernels
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +194,8 @@ def main():
     ap.add_argument("--form", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--nrhs", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-chosen", action="store_true",
+                    help="skip the chosen-form run (FP32 + learned guess) and its error against FP64")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--guess", default="extrap", choices=["extrap", "learned"],
                     help="initial guess of the Z0 solve (learned: the committed network parameters)")
@@ -129,7 +203,7 @@ def main():
                     help="after the timed region, run one 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see DESIGN.md on sharding)",
+        print("bench.py runs on one GPU only: there is no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
 
@@ -141,72 +215,22 @@ def main():
     name = "sphere20480" if args.nrhs == 1 else "sphere20480x64"
     w = workload(name, n_rhs=args.nrhs)
     nr = len(w.pulses)
-    prec = tdbem.FP64 if args.form == "fp64" else tdbem.FP32
-    cfg = tdbem.Config(dt=w.dt, nt=w.nt, theta=w.theta, zeta=w.zeta, leaf_max=w.leaf_max, mode=tdbem.MODE_IFMM,
-                       precision=prec, n_rhs=nr, gmres_rtol=args.rtol, gmres_maxit=60,
-                       guess=tdbem.GUESS_LEARNED if args.guess == "learned" else tdbem.GUESS_EXTRAP)
-    t0 = time.perf_counter()
-    S = tdbem.Solver(w.verts, w.tris, cfg)
-    if args.guess == "learned":
-        from paper_2303_05006_amd.train_guess import DEFAULT_OUT
-        S.guess_weights(np.load(DEFAULT_OUT))
-    torch.cuda.synchronize()
-    setup_s = time.perf_counter() - t0
-    info = S.info()
-    ne = S.ne
     W, K = args.warmup, args.steps
     last = W + K
+    chosen = not args.no_chosen and nr == 1 and args.form == "fp64" and args.guess == "extrap"
+
+    S, setup_s = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol)
+    info = S.info()
+    ne = S.ne
     # incident fields of every step resident in HBM before timing
     V = torch.zeros((last, nr, ne), dtype=torch.float64, device="cuda")
     for a in range(1, last + 1):
         S.incident(w.pulses, a, V[a - 1])
-    J = torch.zeros((nr, ne), dtype=torch.float64, device="cuda")
-    for a in range(1, W + 1):
-        S.step(V[a - 1], J)
-    torch.cuda.synchronize()
-    S.profile(True)
-    iters = []
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for a in range(W + 1, last + 1):
-        S.step(V[a - 1], J)
-        iters.append(S.gmres_iters())
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t1
+    traj = torch.zeros((last, nr, ne), dtype=torch.float64, device="cuda") if chosen else None
+    el, iters = march(torch, S, V, W, K, traj)
     ph = S.phase_times()
-    ms_step = el / K * 1e3
-
-    # algorithmic work in the timed region
-    lmax = info["lmax"]
-    gates = gate_schedule(info["Mt"], lmax, W + 1, last)
-    win = info["window"]
-    m2l_flops = 0.0
-    for l in range(2, lmax + 1):
-        for a in gates[l]:
-            k = a // info["Mt"][l] - 1
-            lags = min(win, k + 1)
-            m2l_flops += info["nilist"][l] * lags * 7 * 2.0 * 256 * 256 * nr
-    vb = 8 if prec == tdbem.FP64 else 4
-    near_bytes = K * (info["near_nnz"] * vb + info["near_pairs"] * 8 + ne * 8 * nr)
-    kernels = {}
-    t_m2l = ph["m2l"][0] * 1e-3
-    t_near = ph["near"][0] * 1e-3
-    if t_m2l > 0:
-        kernels["m2l"] = {"bound": "mfma", "achieved": m2l_flops / t_m2l / 1e12, "unit": "TFLOP/s",
-                          "peak": (PEAK_FP64 if prec == tdbem.FP64 else PEAK_FP32) / 1e12,
-                          "launches": ph["m2l"][1], "ms_total": ph["m2l"][0],
-                          "ms_per_launch": ph["m2l"][0] / max(ph["m2l"][1], 1),
-                          "flop_per_launch": m2l_flops / max(ph["m2l"][1], 1)}
-    if t_near > 0:
-        kernels["near"] = {"bound": "hbm", "achieved": near_bytes / t_near / 1e9, "unit": "GB/s",
-                           "peak": PEAK_HBM / 1e9, "launches": ph["near"][1], "ms_total": ph["near"][0]}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
-    roof = None
-    if dom:
-        kd = kernels[dom]
-        traffic = m2l_traffic(args.form) if (dom == "m2l" and nr == 1) else None
-        roof = {"kernel": dom, "bound": kd["bound"], "achieved": kd["achieved"], "peak": kd["peak"],
-                "unit": kd["unit"], "frac": kd["achieved"] / kd["peak"], "traffic": traffic}
+    prec_fp64 = args.form == "fp64"
+    roof, kernels = kernel_rooflines(info, ph, W, K, nr, prec_fp64, args.form)
     res = {
         "metric": METRIC,
         "value": K / el,
@@ -214,17 +238,19 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": ms_step,
+        "ms_per_step": el / K * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if prec == tdbem.FP64 else "f32",
+        "dtype": "f64" if prec_fp64 else "f32",
         "data": "synthetic",
         "config": {"workload": f"{name}: PEC sphere r=1 m, 20480 triangles / {ne} RWG edges, c dt = 0.02 m, "
                                f"IFMM p_s=p_t=4, leaves <= 64 edges, {nr} incident field(s), steps {W + 1}..{last} of 1000",
                    "form": args.form, "n_rhs": nr, "gmres_rtol": args.rtol, "guess": args.guess},
         "roofline": roof,
         "kernels": kernels,
+        "rhs_steps_per_s": nr * K / el,
+        "near_interactions_per_s": info["near_nnz"] * nr * K / el,
         "phase_ms": {k: v[0] for k, v in ph.items()},
         "phase_launches": {k: v[1] for k, v in ph.items()},
         "gmres_iters_mean": float(np.mean(iters)),
@@ -232,11 +258,27 @@ def main():
         "hierarchy": {k: info[k] for k in ("lmax", "Mt", "ncells", "nilist", "near_nnz", "near_pairs", "z0_nnz", "window")},
         "device_gb": info["device_bytes"] / 1e9,
     }
+    S.close()
+    if chosen:
+        # chosen form on the same incident fields: FP32 near values and M2L
+        # products, learned initial guess; error of its march against FP64's
+        S2, setup2 = make_solver(torch, tdbem, w, "fp32", "learned", args.rtol)
+        traj32 = torch.zeros_like(traj)
+        el2, iters2 = march(torch, S2, V, W, K, traj32)
+        ph2 = S2.phase_times()
+        roof2, kernels2 = kernel_rooflines(S2.info(), ph2, W, K, nr, False, "fp32")
+        err = float(((traj32 - traj) ** 2).sum().sqrt() / (traj ** 2).sum().sqrt())
+        res["chosen"] = {"form": "fp32 near values and M2L + learned initial guess", "value": K / el2,
+                         "unit": "steps/s", "ms_per_step": el2 / K * 1e3, "speedup_vs_fp64": el / el2,
+                         "rel_l2_err_vs_fp64": err, "err_over_steps": f"1..{last}",
+                         "roofline": roof2, "kernels": kernels2,
+                         "phase_ms": {k: v[0] for k, v in ph2.items()},
+                         "gmres_iters_mean": float(np.mean(iters2)), "setup_s": setup2}
+        S2.close()
     if args.copy_probe:
         res["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w)
-    S.close()
     print(json.dumps(res))
 
 

@@ -55,7 +55,13 @@ enum {
 
 enum { TDBEM_MODE_DIRECT = 0, TDBEM_MODE_IFMM = 1 };
 enum { TDBEM_FP64 = 0, TDBEM_FP32 = 1, TDBEM_BF16 = 2 };
-enum { TDBEM_INTERP_LAGRANGE = 0 };
+/* Interpolants on p equispaced nodes (Section 3.2).  LAGRANGE: Lagrange
+ * polynomials in space and time.  CHI_TIME: Lagrange in space; in time the
+ * piecewise cubic Hermite interpolant whose node slopes are finite differences
+ * of the node values (central inside, second-order one-sided at the ends), the
+ * interpolant of the paper's earlier work; it reproduces quadratics and keeps
+ * the late-time march stable where the Lagrange variant is not. */
+enum { TDBEM_INTERP_LAGRANGE = 0, TDBEM_INTERP_CHI_TIME = 1 };
 enum { TDBEM_GUESS_EXTRAP = 0, TDBEM_GUESS_LEARNED = 1 };
 
 typedef struct tdbem_ctx tdbem_ctx;
@@ -75,7 +81,7 @@ typedef struct {
     double eps, mu;           /* permittivity [F/m], permeability [H/m] */
     double theta, zeta;       /* CFIE coupling constants (zeta in 1/s) */
     int32_t p_s, p_t;         /* interpolation points per axis in space and in time (IFMM) */
-    int32_t interp;           /* TDBEM_INTERP_LAGRANGE (equispaced nodes) */
+    int32_t interp;           /* TDBEM_INTERP_LAGRANGE or TDBEM_INTERP_CHI_TIME (IFMM) */
     int32_t leaf_max;         /* subdivide a cell while it holds more edges than this */
     int32_t min_level;        /* subdivide at least down to this level (2) */
     int32_t mu_window;        /* far-field window (paper: 8 future intervals); raised if needed */

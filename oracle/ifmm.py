@@ -18,7 +18,11 @@ electromagnetic scattering problems":
   code uses a finite window), L2L re-interpolation down, tested L2P (Eq. eval,
   with the minus sign of the scalar-potential term of Eq. testing).
 
-Interpolation: Lagrange polynomials on p equispaced nodes omega_n = -1 + 2n/(p-1).
+Interpolation on p equispaced nodes omega_n = -1 + 2n/(p-1): Lagrange
+polynomials in space; in time either Lagrange or the piecewise cubic Hermite
+interpolant with finite-difference node slopes (the interpolant the paper takes
+from its earlier work; it reproduces quadratics, which the window truncation of
+the fast code needs, and is C^1 inside the interval).
 Channels: 0-2 vector potential (kernel dU/dt = c d U^{d-1}, d = 2), 3 scalar
 potential (U^d), 4-6 magnetic vector potential (U^d, grad_y on the source).
 """
@@ -59,6 +63,35 @@ def lagrange(p, xi):
                     t = t * (xi[..., 0] - w[m])
             d = d + t
         der[..., n] = d / den
+    return val, der
+
+
+def chi_fd(p, xi):
+    """Values and derivatives of the cardinal functions of piecewise cubic
+    Hermite interpolation on the p equispaced nodes, with the node slopes taken
+    from finite differences of the node values: central at interior nodes,
+    second-order one-sided (-3 f0 + 4 f1 - f2) / 2h at the ends.  Points outside
+    [-1, 1] use the end pieces.  xi any array, returns [..., p]."""
+    w = nodes(p)
+    h = w[1] - w[0]
+    xi = np.asarray(xi, float)
+    seg = np.clip(np.floor((xi + 1.0) / h).astype(int), 0, p - 2)
+    t = (xi - w[seg]) / h
+    # Hermite basis on the segment and its t-derivative
+    H = [2 * t**3 - 3 * t**2 + 1, t**3 - 2 * t**2 + t, -2 * t**3 + 3 * t**2, t**3 - t**2]
+    dH = [6 * t**2 - 6 * t, 3 * t**2 - 4 * t + 1, -6 * t**2 + 6 * t, 3 * t**2 - 2 * t]
+    val = np.zeros(xi.shape + (p,))
+    der = np.zeros(xi.shape + (p,))
+    for n in range(p):
+        f = np.zeros(p)
+        f[n] = 1.0
+        slope = np.zeros(p)
+        slope[0] = (-3 * f[0] + 4 * f[1] - f[2]) / (2 * h)
+        slope[p - 1] = (3 * f[p - 1] - 4 * f[p - 2] + f[p - 3]) / (2 * h)
+        slope[1:p - 1] = (f[2:] - f[:p - 2]) / (2 * h)
+        fa, fb, sa, sb = f[seg], f[seg + 1], slope[seg], slope[seg + 1]
+        val[..., n] = H[0] * fa + H[1] * h * sa + H[2] * fb + H[3] * h * sb
+        der[..., n] = (dH[0] * fa + dH[1] * h * sa + dH[2] * fb + dH[3] * h * sb) / h
     return val, der
 
 
@@ -176,8 +209,11 @@ def kernel_U(c):
 class IFMM:
     """Far field of the fast TDBEM for a given current history (all-interval M2L)."""
 
-    def __init__(self, mesh, dt, theta, zeta, eps, mu, p_s=4, p_t=4, leaf_max=64, kernels=None):
+    def __init__(self, mesh, dt, theta, zeta, eps, mu, p_s=4, p_t=4, leaf_max=64, kernels=None,
+                 interp_t="lagrange"):
         self.m = mesh
+        assert interp_t in ("lagrange", "chi")
+        self._tcard = (lambda xi: lagrange(self.pt, xi)) if interp_t == "lagrange" else (lambda xi: chi_fd(self.pt, xi))
         self.c = 1.0 / math.sqrt(eps * mu)
         self.eta = math.sqrt(mu / eps)
         self.dt, self.cdt = dt, self.c * dt
@@ -235,7 +271,7 @@ class IFMM:
         for ax in range(3):
             v, _ = lagrange(ps, (cc[ax] + hs_c * w_s - cp[ax]) / hs_p)   # [child node, parent node]
             S.append(v)
-        Tm, _ = lagrange(pt, 0.5 * w_t + (h - 0.5))                      # [child node, parent node]
+        Tm, _ = self._tcard(0.5 * w_t + (h - 0.5))                       # [child node, parent node]
         Sp = np.einsum('ia,jb,kc->ijkabc', S[0], S[1], S[2]).reshape(ps ** 3, ps ** 3)
         return np.kron(Sp, Tm)          # [(child b', n'), (parent b, n)]
 
@@ -264,7 +300,7 @@ class IFMM:
                 if S.leaf:
                     for k in range(K):
                         beta = np.arange(k * M, (k + 1) * M)
-                        lt, _ = lagrange(self.pt, (beta * self.dt - (k + 0.5) * 2 * ht) / ht)   # [beta, n]
+                        lt, _ = self._tcard((beta * self.dt - (k + 0.5) * 2 * ht) / ht)   # [beta, n]
                         Tjn = Jh[beta][:, S.edges].T @ lt                                   # [j, n]
                         mm[k] = np.einsum('jcb,jn->cbn', self.Wm[S.edges], Tjn)
                 else:
@@ -317,7 +353,7 @@ class IFMM:
                             if a > N:
                                 continue
                             xi = (a * self.dt - (kt + 0.5) * 2 * ht) / ht
-                            v, d = lagrange(self.pt, np.array([xi]))
+                            v, d = self._tcard(np.array([xi]))
                             v, d = v[0], d[0] / ht
                             L = lc[kt].reshape(7, n3, self.pt)
                             tw = np.stack([d, d, d, v, d + self.zeta * v, d + self.zeta * v, d + self.zeta * v])  # [7, m]

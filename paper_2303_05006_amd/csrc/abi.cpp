@@ -117,6 +117,8 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg, TDBEM_EINVAL, "null config");
     C->cfg = *cfg;
     TD_REQUIRE(cfg->d == 2, TDBEM_EINVAL, "only the quadratic B-spline (d = 2) is implemented");
+    TD_REQUIRE(cfg->interp == TDBEM_INTERP_LAGRANGE || cfg->interp == TDBEM_INTERP_CHI_TIME, TDBEM_EINVAL,
+               "unknown interpolant");
     TD_REQUIRE(cfg->dt > 0 && cfg->eps > 0 && cfg->mu > 0 && cfg->theta >= 0 && cfg->zeta >= 0, TDBEM_EINVAL,
                "dt, eps, mu must be positive; theta, zeta non-negative");
     TD_REQUIRE(cfg->n_rhs >= 1 && cfg->n_rhs <= 4096, TDBEM_EINVAL, "n_rhs out of range");

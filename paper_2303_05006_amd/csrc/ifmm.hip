@@ -63,7 +63,7 @@ struct FarState {
     double *Wm = nullptr;     // [ne][NCH][NS] P2M weights
     double *El = nullptr;     // [ne][NCH][NS] L2P weights
     double *FAR = nullptr;    // [FR][ne][nrhs] far-field potential per target slot
-    double *S1 = nullptr;     // [2][P][P]: parent cardinal at child node, half h
+    double *S1 = nullptr;     // [space, time][2][P][P]: parent cardinal at child node, half h
 };
 
 // ------------------------------------------------------------ host helpers
@@ -87,6 +87,33 @@ static void lagr(double xi, double *v, double *d) {
         v[n] = prod / den;
         if (d) d[n] = der / den;
     }
+}
+
+// piecewise cubic Hermite interpolation on the equispaced nodes with node slopes
+// from finite differences (central inside, second-order one-sided at the ends):
+// cardinal functions and their derivatives at xi (reproduces quadratics)
+static void chi(double xi, double *v, double *d) {
+    const double h = 2.0 / (P - 1);
+    int i = (int)std::floor((xi + 1.0) / h);
+    i = std::min(std::max(i, 0), P - 2);
+    const double t = (xi - (-1.0 + h * i)) / h;
+    const double h00 = 2 * t * t * t - 3 * t * t + 1, h10 = t * t * t - 2 * t * t + t;
+    const double h01 = -2 * t * t * t + 3 * t * t, h11 = t * t * t - t * t;
+    const double d00 = 6 * t * t - 6 * t, d10 = 3 * t * t - 4 * t + 1, d01 = -6 * t * t + 6 * t, d11 = 3 * t * t - 2 * t;
+    for (int m = 0; m < P; ++m) {
+        double f[P], sl[P];
+        for (int n = 0; n < P; ++n) f[n] = n == m ? 1.0 : 0.0;
+        sl[0] = (-3 * f[0] + 4 * f[1] - f[2]) / (2 * h);
+        sl[P - 1] = (3 * f[P - 1] - 4 * f[P - 2] + f[P - 3]) / (2 * h);
+        for (int n = 1; n < P - 1; ++n) sl[n] = (f[n + 1] - f[n - 1]) / (2 * h);
+        v[m] = h00 * f[i] + h10 * h * sl[i] + h01 * f[i + 1] + h11 * h * sl[i + 1];
+        if (d) d[m] = (d00 * f[i] + d10 * h * sl[i] + d01 * f[i + 1] + d11 * h * sl[i + 1]) / h;
+    }
+}
+
+// temporal cardinal functions of the configured interpolant
+static void tcard(int interp, double xi, double *v, double *d) {
+    if (interp == TDBEM_INTERP_CHI_TIME) chi(xi, v, d); else lagr(xi, v, d);
 }
 
 template <typename T>
@@ -113,6 +140,7 @@ void ifmm_setup(tdbem_ctx *C) {
     TD_REQUIRE(T.lmax >= 2, TDBEM_EINVAL, "IFMM needs at least two levels below the root");
     FarState *F = new FarState();
     C->far = F;
+    const int interp = C->cfg.interp;
     F->lmax = T.lmax;
     F->nrhs = C->nrhs;
     const double ds_max = T.side / std::ldexp(1.0, T.lmax);
@@ -184,7 +212,7 @@ void ifmm_setup(tdbem_ctx *C) {
         std::vector<double> tw((size_t)FL.M * 2 * P), ls((size_t)FL.M * P);
         for (int q = 1; q <= FL.M; ++q) {
             double v[P], d[P];
-            lagr(2.0 * q / FL.M - 1.0, v, d);
+            tcard(interp, 2.0 * q / FL.M - 1.0, v, d);
             for (int m = 0; m < P; ++m) {
                 tw[((size_t)(q - 1) * 2 + 0) * P + m] = v[m];
                 tw[((size_t)(q - 1) * 2 + 1) * P + m] = d[m] / FL.ht;
@@ -192,7 +220,7 @@ void ifmm_setup(tdbem_ctx *C) {
         }
         for (int b = 0; b < FL.M; ++b) {
             double v[P];
-            lagr(2.0 * b / FL.M - 1.0, v, nullptr);
+            tcard(interp, 2.0 * b / FL.M - 1.0, v, nullptr);
             for (int n = 0; n < P; ++n) ls[(size_t)b * P + n] = v[n];
         }
         FL.tw = fup(C, tw);
@@ -271,12 +299,14 @@ void ifmm_setup(tdbem_ctx *C) {
     }
     F->Wm = fup(C, Wm);
     F->El = fup(C, El);
-    std::vector<double> S1(2 * P * P);
+    std::vector<double> S1(4 * P * P);
     for (int h = 0; h < 2; ++h)
         for (int bc = 0; bc < P; ++bc) {
             double v[P];
             lagr((h - 0.5) + 0.5 * (-1.0 + 2.0 * bc / (P - 1)), v, nullptr);
             for (int bp = 0; bp < P; ++bp) S1[(h * P + bp) * P + bc] = v[bp];   // [h][parent][child]
+            tcard(interp, (h - 0.5) + 0.5 * (-1.0 + 2.0 * bc / (P - 1)), v, nullptr);
+            for (int bp = 0; bp < P; ++bp) S1[2 * P * P + (h * P + bp) * P + bc] = v[bp];   // time factor
         }
     F->S1 = fup(C, S1);
     F->FAR = falloc<double>(C, (size_t)F->FR * ne * nr);
@@ -381,7 +411,7 @@ __global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int 
             for (int q = 0; q < NN; ++q) {
                 int q1 = q / (P * P * P), q2 = (q / (P * P)) % P, q3 = (q / P) % P, qn = q % P;
                 double w = S1[(hx * P + b1) * P + q1] * S1[(hy * P + b2) * P + q2] * S1[(hz * P + b3) * P + q3] *
-                           S1[(h * P + n) * P + qn];
+                           S1[2 * P * P + (h * P + n) * P + qn];
                 acc += w * in[q];
             }
         }
@@ -650,7 +680,7 @@ __global__ void __launch_bounds__(256) k_l2l(const int *parent_cells, const int 
         for (int q = 0; q < NN; ++q) {
             int q1 = q / (P * P * P), q2 = (q / (P * P)) % P, q3 = (q / P) % P, qn = q % P;
             double w = S1[(hx * P + q1) * P + a1] * S1[(hy * P + q2) * P + a2] * S1[(hz * P + q3) * P + a3] *
-                       S1[(h * P + qn) * P + m];
+                       S1[2 * P * P + (h * P + qn) * P + m];
             acc += w * in[q];
         }
         PENDc[(((size_t)ch * 2 + h) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = acc;

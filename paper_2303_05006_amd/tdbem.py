@@ -19,6 +19,7 @@ _LIB = None
 # error codes and enums (mirror include/tdbem.h)
 OK, EINVAL, ENOMEM, EHIP, EBREAKDOWN, ENOCONV, EUNSTABLE = 0, -1, -2, -3, -4, -5, -6
 MODE_DIRECT, MODE_IFMM = 0, 1
+INTERP_LAGRANGE, INTERP_CHI_TIME = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
 GUESS_EXTRAP, GUESS_LEARNED = 0, 1
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
@@ -100,6 +101,7 @@ class Config:
     zeta: float = 299792458.0 / 2
     p_s: int = 4
     p_t: int = 4
+    interp: int = INTERP_CHI_TIME
     leaf_max: int = 64
     min_level: int = 2
     mu_window: int = 8
@@ -144,7 +146,7 @@ class Solver:
                   len(self._tris), self._tris.ctypes.data_as(ctypes.c_void_p))
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
-        c = _Config(cfg.dt, cfg.nt, 2, cfg.eps, cfg.mu, cfg.theta, cfg.zeta, cfg.p_s, cfg.p_t, 0,
+        c = _Config(cfg.dt, cfg.nt, 2, cfg.eps, cfg.mu, cfg.theta, cfg.zeta, cfg.p_s, cfg.p_t, cfg.interp,
                     cfg.leaf_max, cfg.min_level, cfg.mu_window, cfg.mode, cfg.precision, cfg.n_rhs,
                     cfg.gmres_rtol, cfg.gmres_maxit, cfg.guess, ctypes.c_void_p(s.cuda_stream))
         h = ctypes.c_void_p()

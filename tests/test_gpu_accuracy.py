@@ -6,12 +6,13 @@ Lagrange), so the difference is interpolation-limited.  Measured here on a
 5120-triangle sphere with the benchmark's c dt and pulse, per step (potentials
 of a marched history) and for the marched current, as the relative l2 error
 sqrt(sum_a |J_a - J_ref,a|^2 / sum_a |J_ref,a|^2) over steps and edges.  The
-bounds below are the measured values rounded up (2.2e-2 for the potentials,
-3.2e-2 for the march).  With the causality guard (TDBEM_CAUSAL_GUARD=1: the
-interval shrunk so that no far pair can interact within one interval although
-basis supports reach beyond their cells) the error barely moves (1.6e-2 /
-2.4e-2): it is the interpolation's, not the dropped same-interval terms'.  The
-FP32 form is measured against the FP64 IFMM on the same march.
+bounds below are the measured values rounded up (temporal CHI-FD, the default:
+2.5e-2 for the potentials, 3.6e-2 for the march; temporal Lagrange: 2.2e-2 and
+3.2e-2).  With the causality guard (TDBEM_CAUSAL_GUARD=1: the interval shrunk so
+that no far pair can interact within one interval although basis supports
+reach beyond their cells) the error barely moves (1.6e-2 / 2.4e-2): it is the
+interpolation's, not the dropped same-interval terms'.  The FP32 form is
+measured against the FP64 IFMM on the same march (4.4e-5).
 """
 import os
 

@@ -30,15 +30,20 @@ def _torch():
     return torch
 
 
-@pytest.fixture(scope="module")
-def setup():
+INTERPS = {tdbem.INTERP_LAGRANGE: "lagrange", tdbem.INTERP_CHI_TIME: "chi"}
+
+
+@pytest.fixture(scope="module", params=[tdbem.INTERP_CHI_TIME, tdbem.INTERP_LAGRANGE], ids=["chi", "lagrange"])
+def setup(request):
     _torch()
+    interp = request.param
     v, f = icosphere(2)
     m = O.Mesh(v, f)
     dt = CDT / C0
     S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=LEAF, gmres_rtol=1e-13,
-                                        gmres_maxit=200))
-    F = IFMM(m, dt, 1.0, C0 / 2, EPS0, MU0, leaf_max=LEAF)
+                                        gmres_maxit=200, interp=interp))
+    S.interp = interp
+    F = IFMM(m, dt, 1.0, C0 / 2, EPS0, MU0, leaf_max=LEAF, interp_t=INTERPS[interp])
     G = O.max_lag(m, CDT) + 1
     Z = O.zrows(m, np.arange(m.ne), CDT, 1.0, C0 / 2, G=G)       # [i, j, g]
     near = np.zeros((m.ne, m.ne), bool)
@@ -130,7 +135,7 @@ def test_batched_rhs_columns_equal_single_runs(setup):
     m, S, F, Z, near, dt = setup
     v, f = icosphere(2)
     B = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=LEAF, n_rhs=3, gmres_rtol=1e-12,
-                                        gmres_maxit=200))
+                                        gmres_maxit=200, interp=S.interp))
     n_hist = 97
     rng = np.random.default_rng(11)
     hist = rng.standard_normal((n_hist, 3, m.ne))
@@ -168,10 +173,10 @@ def test_batched_rhs_columns_equal_single_runs(setup):
 
 
 # ------------------------------------------------------------ precision forms
-def _solver(dt, **kw):
+def _solver(dt, interp, **kw):
     v, f = icosphere(2)
     return tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=LEAF, gmres_rtol=1e-13,
-                                           gmres_maxit=200, **kw))
+                                           gmres_maxit=200, interp=interp, **kw))
 
 
 # The FP32 bound: the far field applies the undifferentiated kernels (U grows
@@ -185,7 +190,7 @@ def test_precision_forms_potentials(setup, prec, tol):
     oracles."""
     torch = _torch()
     m, S, F, Z, near, dt = setup
-    B = _solver(dt, precision=prec)
+    B = _solver(dt, S.interp, precision=prec)
     n_hist = 97
     rng = np.random.default_rng(5)
     hist = rng.standard_normal((n_hist, m.ne))
@@ -207,8 +212,8 @@ def test_fp32_form_batched_equals_single(setup):
     """FP32 form: target-major batched M2L against offset-major single runs."""
     torch = _torch()
     m, S, F, Z, near, dt = setup
-    B = _solver(dt, precision=tdbem.FP32, n_rhs=2)
-    S1 = _solver(dt, precision=tdbem.FP32)
+    B = _solver(dt, S.interp, precision=tdbem.FP32, n_rhs=2)
+    S1 = _solver(dt, S.interp, precision=tdbem.FP32)
     n_hist = 60
     rng = np.random.default_rng(3)
     hist = rng.standard_normal((n_hist, 2, m.ne))
@@ -230,7 +235,7 @@ def test_fp32_form_marched_current_close_to_fp64(setup):
     rounding of the undifferentiated far kernels, not the near field)."""
     torch = _torch()
     m, S, F, Z, near, dt = setup
-    B = _solver(dt, precision=tdbem.FP32)
+    B = _solver(dt, S.interp, precision=tdbem.FP32)
     pulse = gaussian_pulse(150e6, 100e6)
     S.reset()
     V = torch.zeros(m.ne, dtype=torch.float64, device="cuda")

@@ -88,12 +88,37 @@ def _poly(cf):
     return k
 
 
-def test_polynomial_kernel_exactness():
+def test_hermite_interpolant_properties():
+    """The temporal CHI-FD cardinal functions: cardinality at the nodes,
+    reproduction of polynomials of degree <= 2 (values and derivatives, also
+    outside [-1, 1] on the end pieces), continuous derivative at the interior
+    nodes, and not reproducing cubics (so the test can tell it from Lagrange)."""
+    from oracle.ifmm import chi_fd, nodes
+    p = 4
+    w = nodes(p)
+    v, _ = chi_fd(p, w)
+    assert np.allclose(v, np.eye(p), atol=1e-15)
+    x = np.linspace(-1.2, 1.2, 97)
+    v, d = chi_fd(p, x)
+    for c in ([1, 0, 0], [0.3, -1.2, 0], [0.5, 0.7, -2.1]):
+        f = c[0] + c[1] * w + c[2] * w**2
+        assert np.allclose(v @ f, c[0] + c[1] * x + c[2] * x**2, atol=1e-13)
+        assert np.allclose(d @ f, c[1] + 2 * c[2] * x, atol=1e-12)
+    eps = 1e-9
+    for node in w[1:-1]:
+        dl = chi_fd(p, np.array([node - eps]))[1]
+        dr = chi_fd(p, np.array([node + eps]))[1]
+        assert np.allclose(dl, dr, atol=1e-6)
+    assert np.abs(chi_fd(p, x)[0] @ w**3 - x**3).max() > 1e-3
+
+
+@pytest.mark.parametrize("interp_t", ["lagrange", "chi"])
+def test_polynomial_kernel_exactness(interp_t):
     v, f = icosphere(2)
     m = O.Mesh(v, f)
     dt = 0.03 / C0
     theta, zeta = 1.0, C0 / 2
-    F = IFMM(m, dt, theta, zeta, EPS0, MU0, leaf_max=6, kernels=(_poly(P1), _poly(P0)))
+    F = IFMM(m, dt, theta, zeta, EPS0, MU0, leaf_max=6, kernels=(_poly(P1), _poly(P0)), interp_t=interp_t)
     H = F.H
     assert H.lmax >= 3 and H.Mt[H.lmax] >= 3
     nb = 4 * H.Mt[2] + 3
