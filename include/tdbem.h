@@ -141,7 +141,8 @@ enum {
     TDBEM_Q_EDGE_LEAF = 13,  /* int32 [N_e]: internal (leaf-order) position of each canonical edge */
     TDBEM_Q_SETUP_MS = 14,   /* double: wall time of tdbem_setup */
     TDBEM_Q_PHASE_MS = 15,   /* double [TDBEM_NPHASE]: device time per phase since profiling was enabled */
-    TDBEM_Q_PHASE_COUNT = 16 /* int64 [TDBEM_NPHASE]: timed launches per phase */
+    TDBEM_Q_PHASE_COUNT = 16, /* int64 [TDBEM_NPHASE]: timed launches per phase */
+    TDBEM_Q_GUESS_USED = 17  /* int64: (step, rhs) pairs whose solve started from the learned guess */
 };
 
 /* Phases timed by tdbem_profile (HIP events on the work stream around each
@@ -178,8 +179,9 @@ int tdbem_profile(tdbem_ctx *ctx, int32_t enable);
  *   o(x) = relu(relu(x W1 + b1) W2 + b2) . w3 + b3
  * (W1, W2 and the hidden layer rounded to bf16, FP32 accumulation) the guess is
  *   J_guess = extrapolation + s_i (o(x) - o(-x)) / 2.
- * The solve itself stays FP64 and converges to the same tolerance from either
- * guess. */
+ * The solve starts from whichever of this guess and the extrapolation has the
+ * smaller residual norm ||R - Z0 x|| (per right-hand side); it stays FP64 and
+ * converges to the same tolerance from either. */
 #define TDBEM_GUESS_NFEAT 116
 #define TDBEM_GUESS_NHIDDEN 128
 #define TDBEM_GUESS_NPARAMS (116 * 128 + 128 + 128 * 128 + 128 + 128 + 1)

@@ -438,6 +438,14 @@ int tdbem_query(const tdbem_ctx *C, int32_t key, void *out) {
         case TDBEM_Q_STEP: *(int32_t *)out = C->alpha; break;
         case TDBEM_Q_EDGE_LEAF: std::memcpy(out, T.iperm.data(), sizeof(int) * (size_t)C->ne); break;
         case TDBEM_Q_SETUP_MS: *(double *)out = C->setup_ms; break;
+        case TDBEM_Q_GUESS_USED:
+            try {
+                *(int64_t *)out = guess_used(const_cast<tdbem_ctx *>(C));
+            } catch (const Error &e) {
+                set_error(e.msg);
+                return e.code;
+            }
+            break;
         case TDBEM_Q_PHASE_MS:
         case TDBEM_Q_PHASE_COUNT:
             try {

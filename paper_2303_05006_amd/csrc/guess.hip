@@ -16,6 +16,8 @@
 // rounded to bf16, and a 116 -> 128 -> 128 -> 1 ReLU network o(x) gives the odd
 // correction g(x) = (o(x) - o(-x)) / 2 to the quadratic extrapolation:
 //   J_guess = extrap + s_i g(x).
+// The solve starts from whichever of the two guesses has the smaller residual
+// norm ||R - Z0 x|| (per right-hand side), so the extrapolation is the fallback.
 // The matrix products run on the bf16 matrix cores with FP32 accumulation; the
 // biases and the last layer are FP32.
 #include <hip/hip_runtime.h>
@@ -45,7 +47,13 @@ struct GuessState {
     bool ready = false;
     float *cap_feat = nullptr;  // capture: [rhs][ne][116] (canonical order)
     double *cap_aux = nullptr;  // capture: [rhs][ne][2] (scale, extrapolation)
+    double *xl = nullptr;       // [ne][rhs] learned guess
+    double *zxl = nullptr;      // [ne][rhs] Z0 times the learned guess
+    double *part = nullptr;     // [JB][rhs][2] partial residual norms
+    int *use = nullptr;         // [rhs] 1 where the learned guess has the smaller residual
+    int64_t *used = nullptr;    // device count of (step, rhs) where the learned guess was taken
 };
+static constexpr int JB = 256;  // blocks of the residual comparison
 
 // round-to-nearest-even FP32 -> bf16 bits
 __host__ __device__ inline unsigned short bf16_bits(float f) {
@@ -139,6 +147,13 @@ void guess_setup(tdbem_ctx *C) {
     G->b1 = dalloc<float>(C, GNH);
     G->b2 = dalloc<float>(C, GNH);
     G->w3 = dalloc<float>(C, GNH + 1);
+    const size_t nv = (size_t)ne * C->nrhs;
+    G->xl = dalloc<double>(C, nv);
+    G->zxl = dalloc<double>(C, nv);
+    G->part = dalloc<double>(C, (size_t)JB * C->nrhs * 2);
+    G->use = dalloc<int>(C, C->nrhs);
+    G->used = dalloc<int64_t>(C, 1);
+    TD_HIP(hipMemset(G->used, 0, sizeof(int64_t)));
 }
 
 void guess_destroy(tdbem_ctx *C) {
@@ -197,7 +212,8 @@ struct GuessArgs {
     const float *sg;
     const unsigned short *w1, *w2;
     const float *b1, *b2, *w3;
-    double *x;                  // in: extrapolation; out: guess
+    const double *x;            // extrapolation
+    double *xl;                 // out: learned guess
     float *cap_feat;
     double *cap_aux;
 };
@@ -342,7 +358,53 @@ __global__ void __launch_bounds__(256) k_guess(GuessArgs a) {
     const int src = 4 * qd + row;             // lane holding that item's scale (any quarter)
     const float sc = __shfl(scale, src & 15, 64);
     const int64_t it2 = ((int64_t)blockIdx.x * 4 + wave) * 16 + src;
-    if (row < 4 && it2 < nitem) a.x[it2] += (double)sc * (double)g;
+    if (row < 4 && it2 < nitem) a.xl[it2] = a.x[it2] + (double)sc * (double)g;
+}
+
+// residual comparison: part[b][r] = sum over block b's rows of (b - Z0 x)^2 for the
+// extrapolation and for the learned guess
+__global__ void k_judge_part(int ne, int nrhs, const double *rhs, const double *zx, const double *zxl, double *part) {
+    __shared__ double red[2][256];
+    for (int r = 0; r < nrhs; ++r) {
+        double se = 0.0, sl = 0.0;
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += gridDim.x * blockDim.x) {
+            const size_t q = (size_t)i * nrhs + r;
+            const double de = rhs[q] - zx[q], dl = rhs[q] - zxl[q];
+            se += de * de;
+            sl += dl * dl;
+        }
+        red[0][threadIdx.x] = se;
+        red[1][threadIdx.x] = sl;
+        __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                red[0][threadIdx.x] += red[0][threadIdx.x + o];
+                red[1][threadIdx.x] += red[1][threadIdx.x + o];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            part[((size_t)blockIdx.x * nrhs + r) * 2] = red[0][0];
+            part[((size_t)blockIdx.x * nrhs + r) * 2 + 1] = red[1][0];
+        }
+        __syncthreads();
+    }
+}
+// one thread per rhs: sum the partials in a fixed order and decide
+__global__ void k_judge_decide(int nrhs, int nb, const double *part, int *use, int64_t *used) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double se = 0.0, sl = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        se += part[((size_t)b * nrhs + r) * 2];
+        sl += part[((size_t)b * nrhs + r) * 2 + 1];
+    }
+    use[r] = sl < se ? 1 : 0;
+    if (sl < se) atomicAdd((unsigned long long *)used, 1ull);
+}
+__global__ void k_judge_apply(int64_t n, int nrhs, const int *use, const double *xl, double *x) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n && use[k % nrhs]) x[k] = xl[k];
 }
 
 void launch_guess(tdbem_ctx *C, int alpha, hipStream_t s) {
@@ -356,14 +418,31 @@ void launch_guess(tdbem_ctx *C, int alpha, hipStream_t s) {
     a.ring = C->d_Jring; a.rhs = C->d_rhs; a.zx = C->d_tmp; a.dinv = C->d_z0_dinv;
     a.nn = G->nn; a.perm = C->d_perm; a.sg = G->sg;
     a.w1 = G->w1; a.w2 = G->w2; a.b1 = G->b1; a.b2 = G->b2; a.w3 = G->w3;
-    a.x = C->d_x; a.cap_feat = G->cap_feat; a.cap_aux = G->cap_aux;
+    a.x = C->d_x; a.xl = G->xl; a.cap_feat = G->cap_feat; a.cap_aux = G->cap_aux;
     const int64_t nitem = (int64_t)C->ne * C->nrhs;
     const unsigned nb = (unsigned)((nitem + 63) / 64);
-    if (mlp)
-        hipLaunchKernelGGL(k_guess<true>, dim3(nb), dim3(256), 0, s, a);
-    else
+    if (!mlp) {
         hipLaunchKernelGGL(k_guess<false>, dim3(nb), dim3(256), 0, s, a);
+        TD_HIP(hipGetLastError());
+        return;
+    }
+    hipLaunchKernelGGL(k_guess<true>, dim3(nb), dim3(256), 0, s, a);
+    // the residual judges the learned guess; the extrapolation is the fallback
+    launch_spmv(C, G->xl, G->zxl, s);
+    hipLaunchKernelGGL(k_judge_part, dim3(JB), dim3(256), 0, s, C->ne, C->nrhs, C->d_rhs, C->d_tmp, G->zxl, G->part);
+    hipLaunchKernelGGL(k_judge_decide, dim3((C->nrhs + 63) / 64), dim3(64), 0, s, C->nrhs, JB, G->part, G->use,
+                       G->used);
+    hipLaunchKernelGGL(k_judge_apply, dim3((unsigned)((nitem + 255) / 256)), dim3(256), 0, s, nitem, C->nrhs, G->use,
+                       G->xl, C->d_x);
     TD_HIP(hipGetLastError());
+}
+
+int64_t guess_used(tdbem_ctx *C) {
+    if (!C->guess) return 0;
+    int64_t v = 0;
+    TD_HIP(hipMemcpyAsync(&v, C->guess->used, sizeof(int64_t), hipMemcpyDeviceToHost, C->stream));
+    TD_HIP(hipStreamSynchronize(C->stream));
+    return v;
 }
 
 }  // namespace tdbem

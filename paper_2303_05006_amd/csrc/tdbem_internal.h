@@ -199,6 +199,7 @@ void guess_load(tdbem_ctx *C, const float *params, int64_t n);
 void guess_capture(tdbem_ctx *C, float *feat, double *aux);
 bool guess_active(const tdbem_ctx *C);
 void launch_guess(tdbem_ctx *C, int alpha, hipStream_t s);
+int64_t guess_used(tdbem_ctx *C);
 void launch_spmv(const tdbem_ctx *C, const double *x, double *y, hipStream_t s);
 void guess_grad(const float *P, const float *X, const float *Y, int64_t n, float *G, float *loss, hipStream_t s);
 void guess_adam(float *P, const float *G, float *M, float *V, int t, float lr, float b1, float b2, float eps,

@@ -23,7 +23,7 @@ INTERP_LAGRANGE, INTERP_CHI_TIME = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
 GUESS_EXTRAP, GUESS_LEARNED = 0, 1
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
-    Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT = range(17)
+    Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT, Q_GUESS_USED = range(18)
 PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
@@ -234,6 +234,10 @@ class Solver:
         features [n_rhs][N_e][116] float32 and aux [n_rhs][N_e][2] float64
         (scale, extrapolation); no arguments switches capture off."""
         _check(load().tdbem_guess_capture(self._h, _ptr(features), _ptr(aux)))
+
+    def guess_used(self):
+        """(step, rhs) pairs so far whose solve started from the learned guess."""
+        return self.query_i64(Q_GUESS_USED)
 
     def gmres_iters(self):
         return self.query_i32(Q_GMRES_ITERS)

@@ -75,6 +75,10 @@ def train(X, Y, torch, epochs=4, batch=8192, lr=1e-3, seed=0, log=print):
     n = X.shape[0]
     g = torch.Generator(device="cuda").manual_seed(seed + 1)
     var = float(Y.var())
+    # fit y / sigma (unit variance); g is linear in (w3, b3), so scaling them by
+    # sigma afterwards gives the network for y itself
+    sigma = max(var ** 0.5, 1e-30)
+    Y = (Y / sigma).contiguous()
     nb = (n + batch - 1) // batch
     total = epochs * nb
     t = 0
@@ -90,8 +94,12 @@ def train(X, Y, torch, epochs=4, batch=8192, lr=1e-3, seed=0, log=print):
             rate = lr * 0.5 * (1.0 + math.cos(math.pi * (t - 1) / total))
             tdbem.guess_adam(P, G, M, V, t, lr=rate)
             tot += L.double() * len(idx)
-        log(f"epoch {ep}: mse {float(tot) / n:.3e} (target variance {var:.3e})")
-    return P.cpu().numpy()
+        log(f"epoch {ep}: mse {float(tot) / n * var:.3e} (target variance {var:.3e})")
+    p = P.cpu().numpy()
+    nf, nh = tdbem.GUESS_NFEAT, tdbem.GUESS_NHIDDEN
+    o = nf * nh + nh + nh * nh + nh
+    p[o:] *= sigma                  # w3 and b3
+    return p
 
 
 def main():
