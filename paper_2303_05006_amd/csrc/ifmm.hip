@@ -387,9 +387,39 @@ __global__ void __launch_bounds__(256) k_p2m(const int *leaf_cells, const int *e
     }
 }
 
+// One 1-D re-interpolation along axis AX (0..2 space, 3 time) of a 256-vector
+// indexed ((i1 P + i2) P + i3) P + i4: out[.., o, ..] = sum_q A[o][q] in[.., q, ..].
+template <int AX>
+__device__ __forceinline__ double reinterp_axis(const double *in, const double *A, int v) {
+    constexpr int stride = AX == 0 ? P * P * P : AX == 1 ? P * P : AX == 2 ? P : 1;
+    const int o = (v / stride) % P, base = v - o * stride;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) s += A[o * P + q] * in[base + q * stride];
+    return s;
+}
+
+// out = (Ax (x) Ay (x) Az (x) At) in, applied as four 1-D passes through LDS
+// (buf holds the input on entry; A[4][P][P] in LDS).  All 256 threads take part.
+__device__ __forceinline__ double reinterp4(double (*buf)[NN], const double (*A)[P * P], int v) {
+    double t = reinterp_axis<3>(buf[0], A[3], v);
+    __syncthreads();
+    buf[1][v] = t;
+    __syncthreads();
+    t = reinterp_axis<2>(buf[1], A[2], v);
+    buf[0][v] = t;
+    __syncthreads();
+    t = reinterp_axis<1>(buf[0], A[1], v);
+    buf[1][v] = t;
+    __syncthreads();
+    return reinterp_axis<0>(buf[1], A[0], v);
+}
+
 // M2M for the non-leaf cells of a level: MM(S, k) = sum_{children, h} T_{oct,h} MM(child, 2k+h);
 // truncated: h = 0 from the child's truncated MM, h = 1 from its full MM.
-// One block per (parent, channel, rhs, tf); thread = output (b, n).
+// T is the tensor product of the parent's 1-D cardinal functions at the child's
+// nodes, applied axis by axis.  One block per (parent, channel, rhs, tf); thread
+// = output (b, n).
 __global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int *child_beg, const int *child_end,
                                              const int *cix, const double *S1, const double *MMc, int slot0, int slot1,
                                              int WRc, double *MMp, int slot, int WRp, int nrhs) {
@@ -397,23 +427,22 @@ __global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int 
     int c = blockIdx.y % NCH, tf = blockIdx.y / NCH;
     int r = blockIdx.z;
     int v = threadIdx.x;
-    int b1 = v / (P * P * P), b2 = (v / (P * P)) % P, b3 = (v / P) % P, n = v % P;
-    __shared__ double in[NN];
+    __shared__ double buf[2][NN];
+    __shared__ double A[4][P * P];
     double acc = 0.0;
     for (int ch = child_beg[cell]; ch < child_end[cell]; ++ch) {
-        int hx = cix[3 * ch] & 1, hy = cix[3 * ch + 1] & 1, hz = cix[3 * ch + 2] & 1;
+        const int hsx[3] = {cix[3 * ch] & 1, cix[3 * ch + 1] & 1, cix[3 * ch + 2] & 1};
         for (int h = 0; h < 2; ++h) {
             int stf = (tf == 1 && h == 0) ? 1 : 0;
             int sl = h == 0 ? slot0 : slot1;
             __syncthreads();
-            in[v] = MMc[((((size_t)ch * WRc + sl) * 2 + stf) * NCH + c) * nrhs * NN + (size_t)r * NN + v];
-            __syncthreads();
-            for (int q = 0; q < NN; ++q) {
-                int q1 = q / (P * P * P), q2 = (q / (P * P)) % P, q3 = (q / P) % P, qn = q % P;
-                double w = S1[(hx * P + b1) * P + q1] * S1[(hy * P + b2) * P + q2] * S1[(hz * P + b3) * P + q3] *
-                           S1[2 * P * P + (h * P + n) * P + qn];
-                acc += w * in[q];
+            buf[0][v] = MMc[((((size_t)ch * WRc + sl) * 2 + stf) * NCH + c) * nrhs * NN + (size_t)r * NN + v];
+            if (v < 4 * P * P) {
+                const int ax = v / (P * P), e = v % (P * P);     // A[ax][o][q] = S1[h_ax][o][q]
+                A[ax][e] = ax < 3 ? S1[hsx[ax] * P * P + e] : S1[2 * P * P + h * P * P + e];
             }
+            __syncthreads();
+            acc += reinterp4(buf, A, v);
         }
     }
     MMp[((((size_t)cell * WRp + slot) * 2 + tf) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = acc;
@@ -670,53 +699,62 @@ __global__ void __launch_bounds__(256) k_l2l(const int *parent_cells, const int 
     int c = blockIdx.y % NCH, h = blockIdx.y / NCH;
     int r = blockIdx.z;
     int v = threadIdx.x;
-    int a1 = v / (P * P * P), a2 = (v / (P * P)) % P, a3 = (v / P) % P, m = v % P;
-    __shared__ double in[NN];
-    in[v] = LCp[((size_t)cell * NCH + c) * nrhs * NN + (size_t)r * NN + v];
-    __syncthreads();
+    __shared__ double buf[2][NN];
+    __shared__ double A[4][P * P];
+    const double lc = LCp[((size_t)cell * NCH + c) * nrhs * NN + (size_t)r * NN + v];
     for (int ch = child_beg[cell]; ch < child_end[cell]; ++ch) {
-        int hx = cix[3 * ch] & 1, hy = cix[3 * ch + 1] & 1, hz = cix[3 * ch + 2] & 1;
-        double acc = 0.0;
-        for (int q = 0; q < NN; ++q) {
-            int q1 = q / (P * P * P), q2 = (q / (P * P)) % P, q3 = (q / P) % P, qn = q % P;
-            double w = S1[(hx * P + q1) * P + a1] * S1[(hy * P + q2) * P + a2] * S1[(hz * P + q3) * P + a3] *
-                       S1[2 * P * P + (h * P + qn) * P + m];
-            acc += w * in[q];
+        const int hsx[3] = {cix[3 * ch] & 1, cix[3 * ch + 1] & 1, cix[3 * ch + 2] & 1};
+        __syncthreads();
+        buf[0][v] = lc;
+        if (v < 4 * P * P) {
+            // transpose: child output o from parent input q, A[ax][o][q] = S1[h_ax][q][o]
+            const int ax = v / (P * P), o = (v % (P * P)) / P, q = v % P;
+            const int hh = ax < 3 ? hsx[ax] : h;
+            A[ax][o * P + q] = S1[(ax < 3 ? 0 : 2 * P * P) + (hh * P + q) * P + o];
         }
-        PENDc[(((size_t)ch * 2 + h) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = acc;
+        __syncthreads();
+        const double out = reinterp4(buf, A, v);
+        PENDc[(((size_t)ch * 2 + h) * NCH + c) * nrhs * NN + (size_t)r * NN + v] = out;
     }
 }
 
 // L2P: FAR(slot of step alpha') for the edges of a leaf, alpha' = (k+1)M + q, q = 1..M:
-// sum_c sum_a El[i][c][a] sum_m LC[c][a][m] tw_c(m, q); tw: l_m' for channels 0-2,
-// l_m for 3, l_m' + zeta l_m for 4-6.  One thread per (edge, q, rhs).
-__global__ void k_l2p(const int *leaf_cells, int nleaf, const int *ebeg, const int *eend, int k, int M,
-                      const double *tw, double zeta, const double *El, const double *LC, double *FAR, int FR,
-                      int ne, int nrhs, int maxe) {
-    int lid = blockIdx.x;
-    int cell = leaf_cells[lid];
-    int e0 = ebeg[cell], e1 = eend[cell];
-    int nloc = (e1 - e0) * M * nrhs;
-    for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
-        int j = t / (M * nrhs), q = (t / nrhs) % M + 1, r = t % nrhs;
-        int i = e0 + j;
-        const double *tv = tw + (size_t)(q - 1) * 2 * P;
-        double s = 0.0;
-        for (int c = 0; c < NCH; ++c) {
-            double w[P];
-            for (int m = 0; m < P; ++m) w[m] = c < 3 ? tv[P + m] : (c == 3 ? tv[m] : tv[P + m] + zeta * tv[m]);
-            const double *L = LC + ((size_t)cell * NCH + c) * nrhs * NN + (size_t)r * NN;
-            const double *e = El + ((size_t)i * NCH + c) * NS;
-            for (int a = 0; a < NS; ++a) {
-                double lt = 0.0;
-                for (int m = 0; m < P; ++m) lt += L[a * P + m] * w[m];
-                s += e[a] * lt;
+// sum_c sum_a El[i][c][a] Lt[q][c][a], Lt[q][c][a] = sum_m LC[c][a][m] tw_c(m, q); tw: l_m' for
+// channels 0-2, l_m for 3, l_m' + zeta l_m for 4-6.  One block per (leaf, rhs): the
+// leaf's time-contracted expansions Lt are formed once in LDS for a chunk of
+// L2P_QC target steps and shared by all its edges.
+static constexpr int L2P_QC = 8;
+__global__ void __launch_bounds__(256) k_l2p(const int *leaf_cells, const int *ebeg, const int *eend, int k, int M,
+                                             const double *tw, double zeta, const double *El, const double *LC,
+                                             double *FAR, int FR, int ne, int nrhs) {
+    const int cell = leaf_cells[blockIdx.x], r = blockIdx.y;
+    const int e0 = ebeg[cell], nloc = eend[cell] - e0;
+    __shared__ double Lt[L2P_QC][NCH][NS];
+    const double *L = LC + (size_t)cell * NCH * nrhs * NN + (size_t)r * NN;
+    for (int q0 = 1; q0 <= M; q0 += L2P_QC) {
+        const int nq = min(L2P_QC, M - q0 + 1);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nq * NCH * NS; t += blockDim.x) {
+            const int qi = t / (NCH * NS), c = (t / NS) % NCH, a = t % NS;
+            const double *tv = tw + (size_t)(q0 + qi - 1) * 2 * P;
+            const double *l = L + (size_t)c * nrhs * NN + a * P;
+            double s = 0.0;
+            for (int m = 0; m < P; ++m) {
+                const double w = c < 3 ? tv[P + m] : (c == 3 ? tv[m] : tv[P + m] + zeta * tv[m]);
+                s += l[m] * w;
             }
+            Lt[qi][c][a] = s;
         }
-        int alpha = (k + 1) * M + q;
-        FAR[((size_t)((alpha - 1) & (FR - 1)) * ne + i) * nrhs + r] = s;
+        __syncthreads();
+        for (int t = threadIdx.x; t < nloc * nq; t += blockDim.x) {
+            const int j = t / nq, qi = t % nq, i = e0 + j;
+            const double *e = El + (size_t)i * NCH * NS;
+            double s = 0.0;
+            for (int ca = 0; ca < NCH * NS; ++ca) s += e[ca] * (&Lt[qi][0][0])[ca];
+            const int alpha = (k + 1) * M + q0 + qi;
+            FAR[((size_t)((alpha - 1) & (FR - 1)) * ne + i) * nrhs + r] = s;
+        }
     }
-    (void)nleaf; (void)maxe;
 }
 
 __global__ void k_far_apply(int64_t n, double sign, const double *FAR, double *y) {
@@ -778,8 +816,8 @@ void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
         }
         if (FL.nleaf > 0) {
             PhaseScope ps(C->prof, TDBEM_PH_L2P, s);
-            hipLaunchKernelGGL(k_l2p, dim3(FL.nleaf), dim3(256), 0, s, FL.leaf_cells, FL.nleaf, FL.ebeg, FL.eend, k,
-                               FL.M, FL.tw, C->cfg.zeta, F->El, FL.LC, F->FAR, F->FR, C->ne, nr, 0);
+            hipLaunchKernelGGL(k_l2p, dim3(FL.nleaf, nr), dim3(256), 0, s, FL.leaf_cells, FL.ebeg, FL.eend, k, FL.M,
+                               FL.tw, C->cfg.zeta, F->El, FL.LC, F->FAR, F->FR, C->ne, nr);
         }
         TD_HIP(hipGetLastError());
     }

@@ -38,6 +38,16 @@ __device__ __forceinline__ int near_offsets(const int *nl_row, int L, int lane, 
     return carry;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin and each XCD has its own
+// L2: map the launch's blocks so that every XCD works on one contiguous range of
+// rows (neighbouring rows share their source edges).  The grid is a multiple of
+// 8 blocks; returns the virtual block index (>= the real count: no work).
+__device__ __forceinline__ unsigned xcd_block() {
+    const unsigned per = gridDim.x / 8;
+    return (blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+static unsigned grid8(uint64_t nb) { return (unsigned)((nb + 7) / 8 * 8); }
+
 template <typename VT>
 __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
                                                    const int *__restrict__ nl, int L, const int *__restrict__ pj,
@@ -46,7 +56,7 @@ __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict
                                                    double *__restrict__ out) {
     __shared__ int offs[4][NEAR_LMAX];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + wv;
+    const int row = (int)xcd_block() * 4 + wv;
     if (row >= ne) return;
     int *off = offs[wv];
     near_offsets(nl + (size_t)row * L, L, lane, off);
@@ -75,7 +85,7 @@ __global__ void __launch_bounds__(256) k_near_jdsN(int ne, int nrhs, const int *
     __shared__ int offs[4][NEAR_LMAX];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int ngrp = (nrhs + 63) >> 6;
-    const int wave = blockIdx.x * 4 + wv;
+    const int wave = (int)xcd_block() * 4 + wv;
     if (wave >= ne * ngrp) return;
     const int row = wave / ngrp, r = (wave % ngrp) * 64 + lane;
     int *off = offs[wv];
@@ -128,7 +138,7 @@ void launch_near(const tdbem_ctx *C, int alpha, double *out, double scale, hipSt
     (void)scale;
     const bool f64 = C->cfg.precision == TDBEM_FP64;
     if (C->nrhs == 1) {
-        unsigned nb = (unsigned)((C->ne + 3) / 4);
+        unsigned nb = grid8((C->ne + 3) / 4);
         if (f64)
             hipLaunchKernelGGL(k_near_jds1<double>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
                                C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval, C->d_Jring, C->ring - 1, alpha, out);
@@ -137,7 +147,7 @@ void launch_near(const tdbem_ctx *C, int alpha, double *out, double scale, hipSt
                                C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out);
     } else {
         int ngrp = (C->nrhs + 63) / 64;
-        unsigned nb = (unsigned)(((int64_t)C->ne * ngrp + 3) / 4);
+        unsigned nb = grid8(((int64_t)C->ne * ngrp + 3) / 4);
         if (f64)
             hipLaunchKernelGGL(k_near_jdsN<double>, dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_nrow_vbase,
                                C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval, C->d_Jring, C->ring - 1, alpha, out);
