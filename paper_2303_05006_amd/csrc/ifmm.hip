@@ -531,30 +531,31 @@ __device__ __forceinline__ void m2l_apply(typename Mma<T>::acc_t (&acc)[4][2], c
             }
 }
 
-// X[xr][j] = MM[cbase[j] + loff] for the columns j = xj, xj + 2, ... of this
-// thread; all loads are issued before the first LDS write so that one memory
-// latency covers the whole tile.
+// Staging of X: each thread owns row xr and the columns j = xj, xj + 2, ...
+// m2l_fetch issues the global loads of one lag (all in flight together) into
+// registers; m2l_store writes them to LDS.  The kernels fetch the next lag
+// before the current lag's products, so the loads overlap the matrix cores.
+static constexpr int M2L_PRE = M2L_NT / 2;
 template <typename T>
-__device__ __forceinline__ void m2l_stage(T (*X)[M2L_NT + 1], const int64_t *cbase, const double *MM, int64_t loff,
-                                          int xr, int xj) {
+__device__ __forceinline__ void m2l_fetch(T (&pre)[M2L_PRE], const int64_t *cbase, const double *MM, int64_t loff,
+                                          int xj) {
 #pragma unroll
-    for (int h = 0; h < M2L_NT / 2; h += 16) {
-        double v[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t b = cbase[xj + 2 * (h + i)];
-            v[i] = b >= 0 ? MM[b + loff] : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) X[xr][xj + 2 * (h + i)] = (T)v[i];
+    for (int i = 0; i < M2L_PRE; ++i) {
+        const int64_t b = cbase[xj + 2 * i];
+        pre[i] = (T)(b >= 0 ? MM[b + loff] : 0.0);
     }
+}
+template <typename T>
+__device__ __forceinline__ void m2l_store(T (*X)[M2L_NT + 1], const T (&pre)[M2L_PRE], int xr, int xj) {
+#pragma unroll
+    for (int i = 0; i < M2L_PRE; ++i) X[xr][xj + 2 * i] = pre[i];
 }
 
 // offset-major M2L for one right-hand side: one block per (offset, kind, column
 // tile); columns are (interaction-list entry q, channel).  Writes the per-entry
 // contribution YB[q][ch][NN] summed over the window's lags.
 template <typename T>
-__global__ void __launch_bounds__(M2L_THREADS) k_m2l_off(const int *tile_code, const int *tile_kind,
+__global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off(const int *tile_code, const int *tile_kind,
                                                          const int *tile_col0, const int *tile_ncol, const int *col_q,
                                                          const int *col_ch, const int *il_src, const double *MM, int WR,
                                                          int k, int W, double hs, double ht, double cl, double *YB) {
@@ -578,14 +579,19 @@ __global__ void __launch_bounds__(M2L_THREADS) k_m2l_off(const int *tile_code, c
         cbase[tid] = b;
     }
     const int xr = tid & (NN - 1), xj = tid >> 8;
-    for (int lag = 1; lag <= W; ++lag) {
-        int ks = k + 1 - lag;
-        if (ks < 0) break;
-        const int64_t loff = (int64_t)((ks % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + xr;
-        __syncthreads();
-        m2l_stage<T>(X, cbase, MM, loff, xr, xj);
+    const int nlag = min(W, k + 1);               // lags whose source interval exists
+    auto loff = [&](int lag) {
+        return (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + xr;
+    };
+    T pre[M2L_PRE];
+    __syncthreads();                              // cbase visible
+    m2l_fetch(pre, cbase, MM, loff(1), xj);
+    for (int lag = 1; lag <= nlag; ++lag) {
+        __syncthreads();                          // the previous products are done with X and tab
+        m2l_store<T>(X, pre, xr, xj);
         m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, cgt, 2.0 * cl);
         __syncthreads();
+        if (lag < nlag) m2l_fetch(pre, cbase, MM, loff(lag + 1), xj);
         m2l_apply<T>(acc, X, tab, base, wc, lane);
     }
     for (int rb = 0; rb < 4; ++rb)
@@ -611,7 +617,7 @@ __global__ void k_m2l_reduce(int n, const int *il_off, const double *YB, const d
 // target-major M2L for batched right-hand sides: one block per (target, kind,
 // (channel, rhs) tile of 64 columns); items are (interaction-list source, lag).
 template <typename T>
-__global__ void __launch_bounds__(M2L_THREADS) k_m2l_tgt(const int *il_off, const int *il_src, const int *il_code,
+__global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt(const int *il_off, const int *il_src, const int *il_code,
                                                          const double *MM, int WR, int k, int W, double hs, double ht,
                                                          double cl, const double *PEND, double *LC, int nrhs) {
     const int O = blockIdx.x, kind = blockIdx.y;
@@ -632,28 +638,38 @@ __global__ void __launch_bounds__(M2L_THREADS) k_m2l_tgt(const int *il_off, cons
     typename Mma<T>::acc_t acc[4][2];
     for (int rb = 0; rb < 4; ++rb) acc[rb][0] = acc[rb][1] = typename Mma<T>::acc_t{0, 0, 0, 0};
     const int xr = tid & (NN - 1), xj = tid >> 8;
-    for (int q = il_off[O]; q < il_off[O + 1]; ++q) {
-        int S = il_src[q], code = il_code[q];
-        int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
+    // column offsets within one source cell's moments (the source enters per item)
+    if (tid < M2L_NT) {
+        int64_t b = -1;
+        if (tid < ncol) {
+            const int cc = (col0 + tid) / nrhs, r = (col0 + tid) % nrhs;
+            b = ((int64_t)(c0 + cc) * nrhs + r) * NN;
+        }
+        cbase[tid] = b;
+    }
+    // items (interaction-list entry, lag), entries outer
+    const int q0 = il_off[O], nq = il_off[O + 1] - q0;
+    const int nlag = min(W, k + 1);
+    const int nitem = nq * nlag;
+    const int64_t strideS = (int64_t)WR * 2 * NCH * nrhs * NN;
+    auto loff = [&](int it) {
+        const int q = q0 + it / nlag, lag = it % nlag + 1;
+        return (int64_t)il_src[q] * strideS +
+               (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * nrhs * NN + xr;
+    };
+    T pre[M2L_PRE];
+    __syncthreads();                              // cbase visible
+    if (nitem > 0) m2l_fetch(pre, cbase, MM, loff(0), xj);
+    for (int it = 0; it < nitem; ++it) {
+        const int q = q0 + it / nlag, lag = it % nlag + 1;
+        const int code = il_code[q];
+        const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
         __syncthreads();
-        if (tid < M2L_NT) {
-            int64_t b = -1;
-            if (tid < ncol) {
-                int cc = (col0 + tid) / nrhs, r = (col0 + tid) % nrhs;
-                b = (((int64_t)S * WR * 2 * NCH + c0 + cc) * nrhs + r) * NN;
-            }
-            cbase[tid] = b;
-        }
-        for (int lag = 1; lag <= W; ++lag) {
-            int ks = k + 1 - lag;
-            if (ks < 0) break;
-            const int64_t loff = (int64_t)((ks % WR) * 2 + (lag == W ? 1 : 0)) * NCH * nrhs * NN + xr;
-            __syncthreads();
-            m2l_stage<T>(X, cbase, MM, loff, xr, xj);
-            m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, cgt, 2.0 * cl);
-            __syncthreads();
-            m2l_apply<T>(acc, X, tab, base, wc, lane);
-        }
+        m2l_store<T>(X, pre, xr, xj);
+        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, cgt, 2.0 * cl);
+        __syncthreads();
+        if (it + 1 < nitem) m2l_fetch(pre, cbase, MM, loff(it + 1), xj);
+        m2l_apply<T>(acc, X, tab, base, wc, lane);
     }
     for (int rb = 0; rb < 4; ++rb)
         for (int cb = 0; cb < 2; ++cb) {
