@@ -390,17 +390,25 @@ __global__ void k_judge_part(int ne, int nrhs, const double *rhs, const double *
         __syncthreads();
     }
 }
-// one thread per rhs: sum the partials in a fixed order and decide
-__global__ void k_judge_decide(int nrhs, int nb, const double *part, int *use, int64_t *used) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
-    double se = 0.0, sl = 0.0;
-    for (int b = 0; b < nb; ++b) {
-        se += part[((size_t)b * nrhs + r) * 2];
-        sl += part[((size_t)b * nrhs + r) * 2 + 1];
+// one block per rhs: sum the partials by a fixed-order tree and decide
+__global__ void __launch_bounds__(JB) k_judge_decide(int nrhs, const double *part, int *use, int64_t *used) {
+    __shared__ double red[2][JB];
+    const int r = blockIdx.x, t = threadIdx.x;
+    red[0][t] = part[((size_t)t * nrhs + r) * 2];
+    red[1][t] = part[((size_t)t * nrhs + r) * 2 + 1];
+    __syncthreads();
+    for (int o = JB / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            red[0][t] += red[0][t + o];
+            red[1][t] += red[1][t + o];
+        }
+        __syncthreads();
     }
-    use[r] = sl < se ? 1 : 0;
-    if (sl < se) atomicAdd((unsigned long long *)used, 1ull);
+    if (t == 0) {
+        const bool l = red[1][0] < red[0][0];
+        use[r] = l ? 1 : 0;
+        if (l) atomicAdd((unsigned long long *)used, 1ull);
+    }
 }
 __global__ void k_judge_apply(int64_t n, int nrhs, const int *use, const double *xl, double *x) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -430,8 +438,7 @@ void launch_guess(tdbem_ctx *C, int alpha, hipStream_t s) {
     // the residual judges the learned guess; the extrapolation is the fallback
     launch_spmv(C, G->xl, G->zxl, s);
     hipLaunchKernelGGL(k_judge_part, dim3(JB), dim3(256), 0, s, C->ne, C->nrhs, C->d_rhs, C->d_tmp, G->zxl, G->part);
-    hipLaunchKernelGGL(k_judge_decide, dim3((C->nrhs + 63) / 64), dim3(64), 0, s, C->nrhs, JB, G->part, G->use,
-                       G->used);
+    hipLaunchKernelGGL(k_judge_decide, dim3(C->nrhs), dim3(JB), 0, s, C->nrhs, G->part, G->use, G->used);
     hipLaunchKernelGGL(k_judge_apply, dim3((unsigned)((nitem + 255) / 256)), dim3(256), 0, s, nitem, C->nrhs, G->use,
                        G->xl, C->d_x);
     TD_HIP(hipGetLastError());

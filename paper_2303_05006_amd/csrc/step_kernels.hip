@@ -293,9 +293,22 @@ void launch_ring_put(const tdbem_ctx *C, int slot, const double *x, hipStream_t 
     hipLaunchKernelGGL(k_ring_put, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, slot, x, C->d_Jring);
     TD_HIP(hipGetLastError());
 }
+// y = Z0 x with 8 lanes per (row, rhs): coalesced reads of each row's entries
+__global__ void k_spmv8(int ne, int nrhs, const int *ptr, const int *col, const double *val, const double *x, double *y) {
+    const int64_t g = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int sub = threadIdx.x & 7;
+    const bool act = g < (int64_t)ne * nrhs;
+    double s = 0.0;
+    if (act) {
+        const int i = (int)(g / nrhs), r = (int)(g % nrhs);
+        for (int q = ptr[i] + sub; q < ptr[i + 1]; q += 8) s += val[q] * x[(size_t)col[q] * nrhs + r];
+    }
+    for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o, 8);
+    if (act && sub == 0) y[g] = s;
+}
 void launch_spmv(const tdbem_ctx *C, const double *x, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_spmv, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->d_z0_ptr,
-                       C->d_z0_col, C->d_z0_val, x, y);
+    hipLaunchKernelGGL(k_spmv8, dim3(nblk((int64_t)C->ne * C->nrhs * 8, 256)), dim3(256), 0, s, C->ne, C->nrhs,
+                       C->d_z0_ptr, C->d_z0_col, C->d_z0_val, x, y);
     TD_HIP(hipGetLastError());
 }
 void launch_extrap(const tdbem_ctx *C, int alpha, double *x, hipStream_t s) {
