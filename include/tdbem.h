@@ -54,6 +54,13 @@ enum {
 };
 
 enum { TDBEM_MODE_DIRECT = 0, TDBEM_MODE_IFMM = 1 };
+/* Precision forms of the history evaluation (the Z0 solve, the current and
+ * the right-hand side are FP64 in every form).  FP64: everything FP64.  FP32:
+ * near-field coefficients stored in FP32, M2L operator and products in FP32 on
+ * the matrix cores (moments and local expansions FP64).  BF16: near-field
+ * coefficients stored in bf16 (FP64 sums), M2L as in FP32; the far field's
+ * undifferentiated kernels cancel over the window, which amplifies rounding by
+ * about (window steps)^2, so bf16 is not offered for the M2L. */
 enum { TDBEM_FP64 = 0, TDBEM_FP32 = 1, TDBEM_BF16 = 2 };
 /* Interpolants on p equispaced nodes (Section 3.2).  LAGRANGE: Lagrange
  * polynomials in space and time.  CHI_TIME: Lagrange in space; in time the
@@ -63,6 +70,17 @@ enum { TDBEM_FP64 = 0, TDBEM_FP32 = 1, TDBEM_BF16 = 2 };
  * the late-time march stable where the Lagrange variant is not. */
 enum { TDBEM_INTERP_LAGRANGE = 0, TDBEM_INTERP_CHI_TIME = 1 };
 enum { TDBEM_GUESS_EXTRAP = 0, TDBEM_GUESS_LEARNED = 1 };
+
+/* Environment switches read by tdbem_setup (IFMM mode):
+ *   TDBEM_BOX_WIDEN=1     interpolation boxes = cells widened by the largest
+ *                         per-axis reach of a basis support beyond its edge
+ *                         midpoint (no extrapolation of the interpolants; for
+ *                         bodies whose finest cells are not much larger than
+ *                         their edges, e.g. structured cubes, whose march
+ *                         otherwise grows after the pulse);
+ *   TDBEM_CAUSAL_GUARD=1  steps per interval from the cell side minus twice
+ *                         that reach, so that no far pair can interact within
+ *                         one interval (Remark 1 takes the cell side alone). */
 
 typedef struct tdbem_ctx tdbem_ctx;
 

@@ -210,8 +210,15 @@ class IFMM:
     """Far field of the fast TDBEM for a given current history (all-interval M2L)."""
 
     def __init__(self, mesh, dt, theta, zeta, eps, mu, p_s=4, p_t=4, leaf_max=64, kernels=None,
-                 interp_t="lagrange"):
+                 interp_t="lagrange", widen=False):
         self.m = mesh
+        # interpolation boxes: the cells, optionally widened by the largest per-axis
+        # distance from an edge midpoint to a vertex of the edge's two triangles
+        self.delta = 0.0
+        if widen:
+            mid = 0.5 * (mesh.xyz[mesh.edges[:, 0]] + mesh.xyz[mesh.edges[:, 1]])
+            for v in (mesh.edges[:, 0], mesh.edges[:, 1], mesh.efree[:, 0], mesh.efree[:, 1]):
+                self.delta = max(self.delta, float(np.abs(mesh.xyz[v] - mid).max()))
         assert interp_t in ("lagrange", "chi")
         self._tcard = (lambda xi: lagrange(self.pt, xi)) if interp_t == "lagrange" else (lambda xi: chi_fd(self.pt, xi))
         self.c = 1.0 / math.sqrt(eps * mu)
@@ -237,7 +244,7 @@ class IFMM:
         for e in range(m.ne):
             l, ci = leaf[e]
             cen = H.cell_center(l, ci)
-            hs = H.side / 2 ** l / 2
+            hs = H.side / 2 ** l / 2 + self.delta          # node half-width
             for side in (0, 1):
                 t = m.etri[e, side]
                 X, Wq = m.quad_points(t)
@@ -262,8 +269,8 @@ class IFMM:
     def _m2m_matrix(self, l, child, parent, h):
         """Parent cardinal functions at the child's nodes (space x time)."""
         H, ps, pt = self.H, self.ps, self.pt
-        hs_p = H.side / 2 ** l / 2
-        hs_c = hs_p / 2
+        hs_p = H.side / 2 ** l / 2 + self.delta            # node half-widths
+        hs_c = H.side / 2 ** (l + 1) / 2 + self.delta
         cp = H.cell_center(l, parent)
         cc = H.cell_center(l + 1, child)
         w_s, w_t = nodes(ps), nodes(pt)
@@ -380,7 +387,7 @@ class IFMM:
         offset `off` from the target cell at level l and `lag` intervals back."""
         H, ps, pt = self.H, self.ps, self.pt
         d = H.side / 2 ** l
-        hs = d / 2
+        hs = d / 2 + self.delta                             # node half-width
         ht = H.Mt[l] * self.dt / 2
         w_s, w_t = nodes(ps), nodes(pt)
         g = np.stack(np.meshgrid(w_s, w_s, w_s, indexing="ij"), -1).reshape(-1, 3) * hs

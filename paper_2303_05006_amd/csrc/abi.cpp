@@ -256,7 +256,8 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_npair_gl = dupload(C, ngl);
     C->d_coef = d_val;
     C->d_nval = dalloc<double>(C, nnz2);
-    if (cfg->precision != TDBEM_FP64) C->d_nval32 = dalloc<float>(C, nnz2);
+    if (cfg->precision == TDBEM_FP32) C->d_nval32 = dalloc<float>(C, nnz2);
+    if (cfg->precision == TDBEM_BF16) C->d_nval16 = dalloc<unsigned short>(C, nnz2);
     {
         int64_t *d_src = dupload(C, nsrc);
         launch_near_to_jds(C, d_src, d_val, s);

@@ -38,7 +38,7 @@ static constexpr int M2L_NT = 64;  // columns per M2L tile
 
 struct FarLevel {
     int n = 0, M = 0;
-    double ds = 0, hs = 0, ht = 0;
+    double ds = 0, hs = 0, hn = 0, ht = 0;   // cell side, cell half-width, node half-width, time half-width
     int *il_off = nullptr, *il_src = nullptr, *il_code = nullptr;  // interaction lists
     int *ix = nullptr;                                             // [n][3] integer coords
     int *ebeg = nullptr, *eend = nullptr;
@@ -59,11 +59,12 @@ struct FarLevel {
 
 struct FarState {
     int lmax = 0, W = 0, WR = 0, FR = 0, nrhs = 1;
+    double delta = 0;         // widening of the interpolation boxes beyond the cells
     std::vector<FarLevel> lev;
     double *Wm = nullptr;     // [ne][NCH][NS] P2M weights
     double *El = nullptr;     // [ne][NCH][NS] L2P weights
     double *FAR = nullptr;    // [FR][ne][nrhs] far-field potential per target slot
-    double *S1 = nullptr;     // [space, time][2][P][P]: parent cardinal at child node, half h
+    double *S1 = nullptr;     // [parent level][space, time][2][P][P]: parent cardinal at child node, half h
 };
 
 // ------------------------------------------------------------ host helpers
@@ -179,6 +180,22 @@ void ifmm_setup(tdbem_ctx *C) {
     F->FR = FR;
     C->far_ring_need = C->Mt[2] + 4;
     const int nr = C->nrhs;
+    // interpolation boxes: the cell widened by the largest distance (per axis) that
+    // a basis support reaches beyond its edge midpoint, so that every quadrature
+    // point of a cell's edges lies inside its box (no extrapolation)
+    if (const char *g = getenv("TDBEM_BOX_WIDEN"); g && atoi(g) == 1) {
+        double d = 0.0;
+        for (int e = 0; e < C->ne; ++e) {
+            const double *a = &H.xyz[3 * H.edge_v[2 * e]], *b = &H.xyz[3 * H.edge_v[2 * e + 1]];
+            const double *o0 = &H.xyz[3 * H.efree[2 * e]], *o1 = &H.xyz[3 * H.efree[2 * e + 1]];
+            for (int k = 0; k < 3; ++k) {
+                const double m = 0.5 * (a[k] + b[k]);
+                d = std::max(d, std::max(std::max(std::fabs(a[k] - m), std::fabs(b[k] - m)),
+                                         std::max(std::fabs(o0[k] - m), std::fabs(o1[k] - m))));
+            }
+        }
+        F->delta = d;
+    }
     // per-level structure
     for (int l = 2; l <= T.lmax; ++l) {
         const Level &L = T.lev[l];
@@ -187,6 +204,7 @@ void ifmm_setup(tdbem_ctx *C) {
         FL.M = C->Mt[l];
         FL.ds = T.side / std::ldexp(1.0, l);
         FL.hs = 0.5 * FL.ds;
+        FL.hn = FL.hs + F->delta;
         FL.ht = 0.5 * FL.M * C->cfg.dt;
         FL.il_off = fup(C, L.il_off);
         FL.il_src = fup(C, L.il_src);
@@ -258,7 +276,7 @@ void ifmm_setup(tdbem_ctx *C) {
         int e = T.perm[p];
         int l = T.edge_leaf_level[p], cell = T.edge_leaf_cell[p];
         const Level &L = T.lev[l];
-        double ds = T.side / std::ldexp(1.0, l), hs = 0.5 * ds;
+        double ds = T.side / std::ldexp(1.0, l), hs = 0.5 * ds + F->delta;   // node half-width
         double cen[3] = {T.origin[0] + (L.ix[cell] + 0.5) * ds, T.origin[1] + (L.iy[cell] + 0.5) * ds,
                          T.origin[2] + (L.iz[cell] + 0.5) * ds};
         for (int sd = 0; sd < 2; ++sd) {
@@ -299,15 +317,22 @@ void ifmm_setup(tdbem_ctx *C) {
     }
     F->Wm = fup(C, Wm);
     F->El = fup(C, El);
-    std::vector<double> S1(4 * P * P);
-    for (int h = 0; h < 2; ++h)
-        for (int bc = 0; bc < P; ++bc) {
-            double v[P];
-            lagr((h - 0.5) + 0.5 * (-1.0 + 2.0 * bc / (P - 1)), v, nullptr);
-            for (int bp = 0; bp < P; ++bp) S1[(h * P + bp) * P + bc] = v[bp];   // [h][parent][child]
-            tcard(interp, (h - 0.5) + 0.5 * (-1.0 + 2.0 * bc / (P - 1)), v, nullptr);
-            for (int bp = 0; bp < P; ++bp) S1[2 * P * P + (h * P + bp) * P + bc] = v[bp];   // time factor
-        }
+    // re-interpolation factors per parent level l: space [2][P][P] (child node in
+    // the parent's box: ((2h - 1) hs_child + hn_child w) / hn_parent), time [2][P][P]
+    std::vector<double> S1((size_t)(T.lmax + 1) * 4 * P * P, 0.0);
+    for (int l = 2; l < T.lmax; ++l) {
+        const double hsc = T.side / std::ldexp(1.0, l + 2), hnc = hsc + F->delta, hnp = 2.0 * hsc + F->delta;
+        double *S = &S1[(size_t)l * 4 * P * P];
+        for (int h = 0; h < 2; ++h)
+            for (int bc = 0; bc < P; ++bc) {
+                const double w = -1.0 + 2.0 * bc / (P - 1);
+                double v[P];
+                lagr(((2 * h - 1) * hsc + hnc * w) / hnp, v, nullptr);
+                for (int bp = 0; bp < P; ++bp) S[(h * P + bp) * P + bc] = v[bp];   // [h][parent][child]
+                tcard(interp, (h - 0.5) + 0.5 * w, v, nullptr);
+                for (int bp = 0; bp < P; ++bp) S[2 * P * P + (h * P + bp) * P + bc] = v[bp];   // time factor
+            }
+    }
     F->S1 = fup(C, S1);
     F->FAR = falloc<double>(C, (size_t)F->FR * ne * nr);
     ifmm_reset(C);
@@ -484,11 +509,13 @@ static constexpr int M2L_THREADS = 512;    // 8 wavefronts: 4 row blocks of 64 x
 // kernel at spatial lattice vector d - 3 off and time lattice 3 lag + w.
 // kind 0: dU/dt = 2c (c tau - r)_+ / r; kind 1: U = (c tau - r)_+^2 / r.
 template <typename T>
-__device__ void m2l_table(T *tab, int ox, int oy, int oz, int lag, int kind, double gs, double cgt, double c2) {
+__device__ void m2l_table(T *tab, int ox, int oy, int oz, int lag, int kind, double gs, double ds, double cgt,
+                          double c2) {
     for (int e = threadIdx.x; e < KTAB; e += blockDim.x) {
         const int w = e % 7 - 3, d = e / 7;
-        const int v1 = d / 49 - 3 - 3 * ox, v2 = (d / 7) % 7 - 3 - 3 * oy, v3 = d % 7 - 3 - 3 * oz;
-        const double r = gs * sqrt((double)(v1 * v1 + v2 * v2 + v3 * v3));
+        const double v1 = gs * (d / 49 - 3) - ds * ox, v2 = gs * ((d / 7) % 7 - 3) - ds * oy,
+                     v3 = gs * (d % 7 - 3) - ds * oz;
+        const double r = sqrt(v1 * v1 + v2 * v2 + v3 * v3);
         const double u = cgt * (3 * lag + w) - r;
         double kv = 0.0;
         if (u > 0.0 && r > 0.0) kv = kind == 0 ? c2 * u / r : u * u / r;
@@ -558,7 +585,8 @@ template <typename T>
 __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off(const int *tile_code, const int *tile_kind,
                                                          const int *tile_col0, const int *tile_ncol, const int *col_q,
                                                          const int *col_ch, const int *il_src, const double *MM, int WR,
-                                                         int k, int W, double hs, double ht, double cl, double *YB) {
+                                                         int k, int W, double hn, double ds, double ht, double cl,
+                                                         double *YB) {
     const int tile = blockIdx.x;
     const int code = tile_code[tile], kind = tile_kind[tile], col0 = tile_col0[tile], ncol = tile_ncol[tile];
     const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
@@ -569,7 +597,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
     __shared__ int64_t cbase[M2L_NT];
     int base[4];
     m2l_row_base(base, wr, lane);
-    const double gs = hs * (2.0 / (P - 1)), cgt = cl * ht * (2.0 / (P - 1));
+    const double gs = hn * (2.0 / (P - 1)), cgt = cl * ht * (2.0 / (P - 1));
     typename Mma<T>::acc_t acc[4][2];
     for (int rb = 0; rb < 4; ++rb) acc[rb][0] = acc[rb][1] = typename Mma<T>::acc_t{0, 0, 0, 0};
     // MM offset of every column at slot 0 (-1: padding column)
@@ -589,7 +617,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
     for (int lag = 1; lag <= nlag; ++lag) {
         __syncthreads();                          // the previous products are done with X and tab
         m2l_store<T>(X, pre, xr, xj);
-        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, cgt, 2.0 * cl);
+        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, ds, cgt, 2.0 * cl);
         __syncthreads();
         if (lag < nlag) m2l_fetch(pre, cbase, MM, loff(lag + 1), xj);
         m2l_apply<T>(acc, X, tab, base, wc, lane);
@@ -618,8 +646,9 @@ __global__ void k_m2l_reduce(int n, const int *il_off, const double *YB, const d
 // (channel, rhs) tile of 64 columns); items are (interaction-list source, lag).
 template <typename T>
 __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt(const int *il_off, const int *il_src, const int *il_code,
-                                                         const double *MM, int WR, int k, int W, double hs, double ht,
-                                                         double cl, const double *PEND, double *LC, int nrhs) {
+                                                         const double *MM, int WR, int k, int W, double hn, double ds,
+                                                         double ht, double cl, const double *PEND, double *LC,
+                                                         int nrhs) {
     const int O = blockIdx.x, kind = blockIdx.y;
     const int c0 = kind == 0 ? 0 : 3, nc = kind == 0 ? 3 : 4;
     const int ncolt = nc * nrhs;
@@ -634,7 +663,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
     __shared__ int64_t cbase[M2L_NT];
     int base[4];
     m2l_row_base(base, wr, lane);
-    const double gs = hs * (2.0 / (P - 1)), cgt = cl * ht * (2.0 / (P - 1));
+    const double gs = hn * (2.0 / (P - 1)), cgt = cl * ht * (2.0 / (P - 1));
     typename Mma<T>::acc_t acc[4][2];
     for (int rb = 0; rb < 4; ++rb) acc[rb][0] = acc[rb][1] = typename Mma<T>::acc_t{0, 0, 0, 0};
     const int xr = tid & (NN - 1), xj = tid >> 8;
@@ -666,7 +695,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
         const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
         __syncthreads();
         m2l_store<T>(X, pre, xr, xj);
-        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, cgt, 2.0 * cl);
+        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, ds, cgt, 2.0 * cl);
         __syncthreads();
         if (it + 1 < nitem) m2l_fetch(pre, cbase, MM, loff(it + 1), xj);
         m2l_apply<T>(acc, X, tab, base, wc, lane);
@@ -694,8 +723,8 @@ static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
         if (FL.ntile > 0) {
             PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
             hipLaunchKernelGGL(k_m2l_off<T>, dim3(FL.ntile), dim3(M2L_THREADS), 0, s, FL.tile_code, FL.tile_kind,
-                               FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, F->WR, k, F->W, FL.hs,
-                               FL.ht, C->c, FL.YB);
+                               FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, F->WR, k, F->W, FL.hn,
+                               FL.ds, FL.ht, C->c, FL.YB);
         }
         PhaseScope ps(C->prof, TDBEM_PH_M2L_SUM, s);
         hipLaunchKernelGGL(k_m2l_reduce, dim3(FL.n, NCH), dim3(NN), 0, s, FL.n, FL.il_off, FL.YB, FL.PEND, (k + 1) & 1,
@@ -703,7 +732,8 @@ static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
     } else {
         PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
         hipLaunchKernelGGL(k_m2l_tgt<T>, dim3(FL.n, 2, (4 * nr + M2L_NT - 1) / M2L_NT), dim3(M2L_THREADS), 0, s,
-                           FL.il_off, FL.il_src, FL.il_code, FL.MM, F->WR, k, F->W, FL.hs, FL.ht, C->c, FL.PEND, FL.LC, nr);
+                           FL.il_off, FL.il_src, FL.il_code, FL.MM, F->WR, k, F->W, FL.hn, FL.ds, FL.ht, C->c, FL.PEND, FL.LC,
+                           nr);
     }
 }
 
@@ -813,7 +843,7 @@ void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
             PhaseScope ps(C->prof, TDBEM_PH_M2M, s);
             FarLevel &CL = F->lev[l + 1];
             hipLaunchKernelGGL(k_m2m, dim3(FL.nparent, 2 * NCH, nr), dim3(NN), 0, s, FL.parent_cells, FL.child_beg,
-                               FL.child_end, CL.ix, F->S1, CL.MM, (2 * k) % F->WR, (2 * k + 1) % F->WR, F->WR, FL.MM,
+                               FL.child_end, CL.ix, F->S1 + (size_t)l * 4 * P * P, CL.MM, (2 * k) % F->WR, (2 * k + 1) % F->WR, F->WR, FL.MM,
                                slot, F->WR, nr);
         }
         TD_HIP(hipGetLastError());
@@ -828,7 +858,7 @@ void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
             PhaseScope ps(C->prof, TDBEM_PH_L2L, s);
             FarLevel &CL = F->lev[l + 1];
             hipLaunchKernelGGL(k_l2l, dim3(FL.nparent, 2 * NCH, nr), dim3(NN), 0, s, FL.parent_cells, FL.child_beg,
-                               FL.child_end, CL.ix, F->S1, FL.LC, CL.PEND, nr);
+                               FL.child_end, CL.ix, F->S1 + (size_t)l * 4 * P * P, FL.LC, CL.PEND, nr);
         }
         if (FL.nleaf > 0) {
             PhaseScope ps(C->prof, TDBEM_PH_L2P, s);

@@ -21,6 +21,19 @@ namespace tdbem {
 // number of pairs with a strip longer than l; off_l is its prefix sum.
 static constexpr int NEAR_LMAX = 512;
 
+// bf16 storage of near-field coefficients (BF16 form): round to nearest even on
+// the way in, exact widening on the way out; the sums stay FP64
+struct bf16s {
+    unsigned short b;
+    bf16s() = default;
+    __device__ explicit bf16s(double v) {
+        unsigned int u = __float_as_uint((float)v);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        b = (unsigned short)(u >> 16);
+    }
+    __device__ explicit operator double() const { return (double)__uint_as_float((unsigned int)b << 16); }
+};
+
 __device__ __forceinline__ int near_offsets(const int *nl_row, int L, int lane, int *off) {
     // exclusive prefix sums of nl_row[0..L) into off[], 64 lags per pass
     int carry = 0;
@@ -131,31 +144,35 @@ void launch_near_to_jds(const tdbem_ctx *C, const int64_t *src_off, const double
     if (C->d_nval32)
         hipLaunchKernelGGL(k_near_to_jds<float>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
                            C->d_nl, C->near_L, C->d_npair_gl, src_off, src, C->d_nval32);
+    if (C->d_nval16)
+        hipLaunchKernelGGL(k_near_to_jds<bf16s>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+                           C->d_nl, C->near_L, C->d_npair_gl, src_off, src, (bf16s *)C->d_nval16);
+    TD_HIP(hipGetLastError());
+}
+
+template <typename VT>
+static void launch_near_t(const tdbem_ctx *C, const VT *val, int alpha, double *out, hipStream_t s) {
+    if (C->nrhs == 1) {
+        unsigned nb = grid8((C->ne + 3) / 4);
+        hipLaunchKernelGGL(k_near_jds1<VT>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase, C->d_nl,
+                           C->near_L, C->d_npair_j, C->d_npair_gl, val, C->d_Jring, C->ring - 1, alpha, out);
+    } else {
+        int ngrp = (C->nrhs + 63) / 64;
+        unsigned nb = grid8(((int64_t)C->ne * ngrp + 3) / 4);
+        hipLaunchKernelGGL(k_near_jdsN<VT>, dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_nrow_vbase,
+                           C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, C->d_Jring, C->ring - 1, alpha, out);
+    }
     TD_HIP(hipGetLastError());
 }
 
 void launch_near(const tdbem_ctx *C, int alpha, double *out, double scale, hipStream_t s) {
     (void)scale;
-    const bool f64 = C->cfg.precision == TDBEM_FP64;
-    if (C->nrhs == 1) {
-        unsigned nb = grid8((C->ne + 3) / 4);
-        if (f64)
-            hipLaunchKernelGGL(k_near_jds1<double>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
-                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval, C->d_Jring, C->ring - 1, alpha, out);
-        else
-            hipLaunchKernelGGL(k_near_jds1<float>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
-                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out);
-    } else {
-        int ngrp = (C->nrhs + 63) / 64;
-        unsigned nb = grid8(((int64_t)C->ne * ngrp + 3) / 4);
-        if (f64)
-            hipLaunchKernelGGL(k_near_jdsN<double>, dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_nrow_vbase,
-                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval, C->d_Jring, C->ring - 1, alpha, out);
-        else
-            hipLaunchKernelGGL(k_near_jdsN<float>, dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_nrow_vbase,
-                               C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, C->d_nval32, C->d_Jring, C->ring - 1, alpha, out);
-    }
-    TD_HIP(hipGetLastError());
+    if (C->cfg.precision == TDBEM_FP64)
+        launch_near_t<double>(C, C->d_nval, alpha, out, s);
+    else if (C->cfg.precision == TDBEM_FP32)
+        launch_near_t<float>(C, C->d_nval32, alpha, out, s);
+    else
+        launch_near_t<bf16s>(C, (const bf16s *)C->d_nval16, alpha, out, s);
 }
 
 // --------------------------------------------------------------- helpers

@@ -135,7 +135,8 @@ struct tdbem_ctx {
     int *d_npair_j = nullptr;       // [pairs] source edge (leaf order)
     int *d_npair_gl = nullptr;      // [pairs] first stored lag | strip length << 16
     double *d_nval = nullptr;       // [nnz] FP64 values
-    float *d_nval32 = nullptr;      // [nnz] FP32 copy (precision forms)
+    float *d_nval32 = nullptr;      // [nnz] FP32 copy (FP32 form)
+    void *d_nval16 = nullptr;       // [nnz] bf16 copy (BF16 form)
     double *d_coef = nullptr;       // pair-major coefficients of every pair (all lags), for inspection
     int max_lag = 0;
 

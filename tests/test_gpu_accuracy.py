@@ -14,6 +14,7 @@ reach beyond their cells) the error barely moves (1.6e-2 / 2.4e-2): it is the
 interpolation's, not the dropped same-interval terms'.  The FP32 form is
 measured against the FP64 IFMM on the same march (4.4e-5).
 """
+import math
 import os
 
 import numpy as np
@@ -107,3 +108,33 @@ def test_fp32_form_marched_current_against_fp64_ifmm(runs):
     e = _rel(J32, Ji)
     print(f"marched current, FP32 form vs FP64 IFMM: rel l2 {e:.2e}")
     assert e < 1e-4
+
+
+def test_precision_forms_on_a_cube():
+    """Precision forms on a structured cube of side 2 m (19200 triangles,
+    c dt = 0.02 m, 300 / 200 MHz pulse along +z, 400 steps): the marched current
+    of the FP32 form and of the BF16 form (bf16 near-field coefficients) against
+    the FP64 IFMM.  The cube's finest cells are smaller than its basis
+    supports reach, and its march grows after the pulse with cell-sized
+    interpolation boxes; the boxes are widened here (TDBEM_BOX_WIDEN=1), with
+    which the march decays."""
+    from paper_2303_05006_amd.inputs import cube
+    torch = _torch()
+    v, f = cube(40, 2.0)
+    dt = CDT / C0
+    pulse = gaussian_pulse(300e6, 200e6, r_max=math.sqrt(3.0))
+    res = {}
+    for name, prec in (("fp64", tdbem.FP64), ("fp32", tdbem.FP32), ("bf16", tdbem.BF16)):
+        os.environ["TDBEM_BOX_WIDEN"] = "1"
+        try:
+            S = tdbem.Solver(v, f, tdbem.Config(dt=dt, nt=NT, mode=tdbem.MODE_IFMM, precision=prec, gmres_rtol=1e-12,
+                                                gmres_maxit=200))
+        finally:
+            os.environ.pop("TDBEM_BOX_WIDEN", None)
+        res[name] = _march(S, pulse, NT, torch)
+        S.close()
+    e32 = _rel(res["fp32"], res["fp64"])
+    e16 = _rel(res["bf16"], res["fp64"])
+    print(f"cube 19200 triangles: FP32 form {e32:.2e}, BF16 form {e16:.2e} (relative l2 against FP64)")
+    assert e32 < 1e-4
+    assert e16 < 1e-2

@@ -251,3 +251,43 @@ def test_fp32_form_marched_current_close_to_fp64(setup):
     print(f"FP32 form vs FP64: max |dJ| / max |J| = {worst / jmax:.2e}")
     assert worst / jmax < 5e-4
     B.close()
+
+
+def test_widened_boxes_potentials_match_oracle():
+    """Interpolation boxes widened by the largest support protrusion
+    (TDBEM_BOX_WIDEN=1) against near + all-interval far of O2 with the same
+    boxes: 1920-edge sphere, leaves of at most 64 edges (two levels), c dt =
+    0.078 m, temporal CHI-FD, 30 steps of random history."""
+    import os
+    torch = _torch()
+    v, f = icosphere(3)
+    m = O.Mesh(v, f)
+    dt = 0.078 / C0
+    os.environ["TDBEM_BOX_WIDEN"] = "1"
+    try:
+        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=64, gmres_rtol=1e-13,
+                                            gmres_maxit=200))
+    finally:
+        os.environ.pop("TDBEM_BOX_WIDEN", None)
+    F = IFMM(m, dt, 1.0, C0 / 2, EPS0, MU0, leaf_max=64, interp_t="chi", widen=True)
+    assert F.delta > 0
+    n_hist = 30
+    rng = np.random.default_rng(30)
+    hist = rng.standard_normal((n_hist, m.ne))
+    a = n_hist + 1
+    near = np.zeros((m.ne, m.ne), bool)
+    for i, j in F.H.near_pairs():
+        near[i, j] = True
+    G = O.max_lag(m, 0.078) + 1
+    Z = O.zrows(m, np.arange(m.ne), 0.078, 1.0, C0 / 2, G=G)
+    Zn = Z * near[:, :, None]
+    ref = F.far_history(hist)[a - 1]
+    for g in range(2, Z.shape[2]):
+        if 0 <= a - g < n_hist:
+            ref += Zn[:, :, g] @ hist[a - g]
+    out = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+    S.potentials(torch.tensor(hist, device="cuda"), n_hist, out)
+    rel = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
+    print(f"widened boxes: rel err {rel:.2e}")
+    S.close()
+    assert rel < 1e-10

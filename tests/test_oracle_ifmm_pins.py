@@ -112,13 +112,15 @@ def test_hermite_interpolant_properties():
     assert np.abs(chi_fd(p, x)[0] @ w**3 - x**3).max() > 1e-3
 
 
-@pytest.mark.parametrize("interp_t", ["lagrange", "chi"])
-def test_polynomial_kernel_exactness(interp_t):
+@pytest.mark.parametrize("interp_t,widen", [("lagrange", False), ("chi", False), ("chi", True)])
+def test_polynomial_kernel_exactness(interp_t, widen):
     v, f = icosphere(2)
     m = O.Mesh(v, f)
     dt = 0.03 / C0
     theta, zeta = 1.0, C0 / 2
-    F = IFMM(m, dt, theta, zeta, EPS0, MU0, leaf_max=6, kernels=(_poly(P1), _poly(P0)), interp_t=interp_t)
+    F = IFMM(m, dt, theta, zeta, EPS0, MU0, leaf_max=6, kernels=(_poly(P1), _poly(P0)), interp_t=interp_t,
+             widen=widen)
+    assert (F.delta > 0) == widen
     H = F.H
     assert H.lmax >= 3 and H.Mt[H.lmax] >= 3
     nb = 4 * H.Mt[2] + 3
