@@ -277,6 +277,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->ring = R;
     const size_t nv = (size_t)ne * C->nrhs;
     C->d_Jring = dalloc<double>(C, (size_t)ne * R * C->nrhs);
+    if (cfg->precision != TDBEM_FP64) C->d_Jring32 = dalloc<float>(C, (size_t)ne * R * C->nrhs);
     C->d_rhs = dalloc<double>(C, nv);
     C->d_x = dalloc<double>(C, nv);
     C->d_tmp = dalloc<double>(C, nv);
@@ -288,6 +289,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_scal = dalloc<double>(C, 64 * (size_t)C->nrhs);
     C->d_pulse = dalloc<double>(C, 11 * (size_t)C->nrhs);
     TD_HIP(hipMemsetAsync(C->d_Jring, 0, (size_t)ne * R * C->nrhs * sizeof(double), s));
+    if (C->d_Jring32) TD_HIP(hipMemsetAsync(C->d_Jring32, 0, (size_t)ne * R * C->nrhs * sizeof(float), s));
     TD_HIP(hipStreamSynchronize(s));
     C->alpha = 1;
     C->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -296,6 +298,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
 static void reset_impl(tdbem_ctx *C) {
     hipStream_t s = C->stream;
     TD_HIP(hipMemsetAsync(C->d_Jring, 0, (size_t)C->ne * C->ring * C->nrhs * sizeof(double), s));
+    if (C->d_Jring32) TD_HIP(hipMemsetAsync(C->d_Jring32, 0, (size_t)C->ne * C->ring * C->nrhs * sizeof(float), s));
     if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_reset(C);
     C->alpha = 1;
 }

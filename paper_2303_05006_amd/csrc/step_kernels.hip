@@ -61,11 +61,11 @@ __device__ __forceinline__ unsigned xcd_block() {
 }
 static unsigned grid8(uint64_t nb) { return (unsigned)((nb + 7) / 8 * 8); }
 
-template <typename VT>
+template <typename VT, typename JT>
 __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
                                                    const int *__restrict__ nl, int L, const int *__restrict__ pj,
                                                    const int *__restrict__ pgl, const VT *__restrict__ val,
-                                                   const double *__restrict__ ring, int ring_mask, int alpha,
+                                                   const JT *__restrict__ ring, int ring_mask, int alpha,
                                                    double *__restrict__ out) {
     __shared__ int offs[4][NEAR_LMAX];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -80,20 +80,20 @@ __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict
     for (int p = lane; p < np; p += 64) {
         const int j = pj[pb + p], gl = pgl[pb + p];
         const int g0 = gl & 0xffff, len = gl >> 16;
-        const double *J = ring + (size_t)j * R;
+        const JT *J = ring + (size_t)j * R;
         const int b = alpha - g0;
-        for (int l = 0; l < len; ++l) acc += (double)v[off[l] + p] * J[(b - l) & ring_mask];
+        for (int l = 0; l < len; ++l) acc += (double)v[off[l] + p] * (double)J[(b - l) & ring_mask];
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) out[row] = acc;
 }
 
 // batched right-hand sides: one wavefront per (row, group of 64 rhs); lanes are rhs
-template <typename VT>
+template <typename VT, typename JT>
 __global__ void __launch_bounds__(256) k_near_jdsN(int ne, int nrhs, const int *__restrict__ row_ptr,
                                                    const int64_t *__restrict__ row_vbase, const int *__restrict__ nl, int L,
                                                    const int *__restrict__ pj, const int *__restrict__ pgl,
-                                                   const VT *__restrict__ val, const double *__restrict__ ring, int ring_mask,
+                                                   const VT *__restrict__ val, const JT *__restrict__ ring, int ring_mask,
                                                    int alpha, double *__restrict__ out) {
     __shared__ int offs[4][NEAR_LMAX];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -111,9 +111,9 @@ __global__ void __launch_bounds__(256) k_near_jdsN(int ne, int nrhs, const int *
     for (int p = 0; p < np; ++p) {
         const int j = pj[pb + p], gl = pgl[pb + p];
         const int g0 = gl & 0xffff, len = gl >> 16;
-        const double *J = ring + (size_t)j * R * nrhs + (act ? r : 0);
+        const JT *J = ring + (size_t)j * R * nrhs + (act ? r : 0);
         const int b = alpha - g0;
-        for (int l = 0; l < len; ++l) acc += (double)v[off[l] + p] * J[(size_t)((b - l) & ring_mask) * nrhs];
+        for (int l = 0; l < len; ++l) acc += (double)v[off[l] + p] * (double)J[(size_t)((b - l) & ring_mask) * nrhs];
     }
     if (act) out[(size_t)row * nrhs + r] = acc;
 }
@@ -150,29 +150,31 @@ void launch_near_to_jds(const tdbem_ctx *C, const int64_t *src_off, const double
     TD_HIP(hipGetLastError());
 }
 
-template <typename VT>
-static void launch_near_t(const tdbem_ctx *C, const VT *val, int alpha, double *out, hipStream_t s) {
+template <typename VT, typename JT>
+static void launch_near_t(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
     if (C->nrhs == 1) {
         unsigned nb = grid8((C->ne + 3) / 4);
-        hipLaunchKernelGGL(k_near_jds1<VT>, dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase, C->d_nl,
-                           C->near_L, C->d_npair_j, C->d_npair_gl, val, C->d_Jring, C->ring - 1, alpha, out);
+        hipLaunchKernelGGL((k_near_jds1<VT, JT>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+                           C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
     } else {
         int ngrp = (C->nrhs + 63) / 64;
         unsigned nb = grid8(((int64_t)C->ne * ngrp + 3) / 4);
-        hipLaunchKernelGGL(k_near_jdsN<VT>, dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr, C->d_nrow_vbase,
-                           C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, C->d_Jring, C->ring - 1, alpha, out);
+        hipLaunchKernelGGL((k_near_jdsN<VT, JT>), dim3(nb), dim3(256), 0, s, C->ne, C->nrhs, C->d_nrow_ptr,
+                           C->d_nrow_vbase, C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1,
+                           alpha, out);
     }
     TD_HIP(hipGetLastError());
 }
 
 void launch_near(const tdbem_ctx *C, int alpha, double *out, double scale, hipStream_t s) {
     (void)scale;
+    // the reduced forms read an FP32 copy of the current ring (half the gather traffic)
     if (C->cfg.precision == TDBEM_FP64)
-        launch_near_t<double>(C, C->d_nval, alpha, out, s);
+        launch_near_t<double, double>(C, C->d_nval, C->d_Jring, alpha, out, s);
     else if (C->cfg.precision == TDBEM_FP32)
-        launch_near_t<float>(C, C->d_nval32, alpha, out, s);
+        launch_near_t<float, float>(C, C->d_nval32, C->d_Jring32, alpha, out, s);
     else
-        launch_near_t<bf16s>(C, (const bf16s *)C->d_nval16, alpha, out, s);
+        launch_near_t<bf16s, float>(C, (const bf16s *)C->d_nval16, C->d_Jring32, alpha, out, s);
 }
 
 // --------------------------------------------------------------- helpers
@@ -196,11 +198,13 @@ __global__ void k_axpby(int64_t n, double a, const double *x, double b, double *
     if (k < n) y[k] = a * x[k] + b * y[k];
 }
 // ring slot write: ring[e][slot][r] = x[e][r]
-__global__ void k_ring_put(int ne, int nrhs, int R, int slot, const double *x, double *ring) {
+__global__ void k_ring_put(int ne, int nrhs, int R, int slot, const double *x, double *ring, float *ring32) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= (int64_t)ne * nrhs) return;
     int e = (int)(k / nrhs), r = (int)(k % nrhs);
-    ring[((size_t)e * R + slot) * nrhs + r] = x[k];
+    const size_t q = ((size_t)e * R + slot) * nrhs + r;
+    ring[q] = x[k];
+    if (ring32) ring32[q] = (float)x[k];
 }
 // quadratic extrapolation x = 3 J^{a-2} - 3 J^{a-3} + J^{a-4} (zero history before 0)
 __global__ void k_extrap(int ne, int nrhs, int R, int alpha, const double *ring, double *x) {
@@ -307,7 +311,8 @@ void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hip
     TD_HIP(hipGetLastError());
 }
 void launch_ring_put(const tdbem_ctx *C, int slot, const double *x, hipStream_t s) {
-    hipLaunchKernelGGL(k_ring_put, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, slot, x, C->d_Jring);
+    hipLaunchKernelGGL(k_ring_put, dim3(nblk((int64_t)C->ne * C->nrhs, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, slot, x,
+                       C->d_Jring, C->d_Jring32);
     TD_HIP(hipGetLastError());
 }
 // y = Z0 x with 8 lanes per (row, rhs): coalesced reads of each row's entries

@@ -148,6 +148,7 @@ struct tdbem_ctx {
 
     // march state
     double *d_Jring = nullptr;      // [ne][ring][nrhs]
+    float *d_Jring32 = nullptr;     // FP32 copy for the near field of the reduced-precision forms
     double *d_rhs = nullptr;        // [ne][nrhs] right-hand side of the step
     double *d_x = nullptr;          // [ne][nrhs] current solution (leaf order)
     double *d_work = nullptr;       // GMRES workspace
