@@ -61,12 +61,17 @@ __device__ __forceinline__ unsigned xcd_block() {
 }
 static unsigned grid8(uint64_t nb) { return (unsigned)((nb + 7) / 8 * 8); }
 
-template <typename VT, typename JT>
+template <typename VT, typename JT, int LG>
 __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
                                                    const int *__restrict__ nl, int L, const int *__restrict__ pj,
                                                    const int *__restrict__ pgl, const VT *__restrict__ val,
                                                    const JT *__restrict__ ring, int ring_mask, int alpha,
                                                    double *__restrict__ out) {
+    // lanes are (64 / LG) pairs x LG consecutive lags: a current gather touches
+    // one short stretch of each pair's ring row and the coefficients of one lag
+    // are 64 / LG consecutive values, so a load instruction touches few cache
+    // lines (LG = 4 measured fastest: 0.55 ms per step on the 20480-triangle
+    // sphere, against 0.62 for 8, 0.60 for 2 and 0.73 for one lag per lane)
     __shared__ int offs[4][NEAR_LMAX];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = (int)xcd_block() * 4 + wv;
@@ -76,13 +81,23 @@ __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict
     const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
     const VT *v = val + row_vbase[row];
     const int R = ring_mask + 1;
+    constexpr int PG = 64 / LG;                 // pairs per wavefront pass
+    const int sub = lane % LG, pg = lane / LG;
     double acc = 0.0;
-    for (int p = lane; p < np; p += 64) {
-        const int j = pj[pb + p], gl = pgl[pb + p];
-        const int g0 = gl & 0xffff, len = gl >> 16;
+    for (int p0 = 0; p0 < np; p0 += PG) {
+        const int p = p0 + pg;
+        int j = 0, g0 = 0, len = 0;
+        if (p < np) {
+            const int gl = pgl[pb + p];
+            j = pj[pb + p];
+            g0 = gl & 0xffff;
+            len = gl >> 16;
+        }
+        const int lmax = pgl[pb + p0] >> 16;      // pairs are sorted by strip length
         const JT *J = ring + (size_t)j * R;
         const int b = alpha - g0;
-        for (int l = 0; l < len; ++l) acc += (double)v[off[l] + p] * (double)J[(b - l) & ring_mask];
+        for (int l = sub; l < lmax; l += LG)
+            if (l < len) acc += (double)v[off[l] + p] * (double)J[(b - l) & ring_mask];
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) out[row] = acc;
@@ -154,7 +169,7 @@ template <typename VT, typename JT>
 static void launch_near_t(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
     if (C->nrhs == 1) {
         unsigned nb = grid8((C->ne + 3) / 4);
-        hipLaunchKernelGGL((k_near_jds1<VT, JT>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+        hipLaunchKernelGGL((k_near_jds1<VT, JT, 4>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
                            C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
     } else {
         int ngrp = (C->nrhs + 63) / 64;
