@@ -284,6 +284,9 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_work = dalloc<double>(C, std::max(gmres_work_doubles(C, std::max(1, cfg->gmres_maxit)),
                                            gmres_coop_work_doubles(ne)));
     C->d_iflag = dalloc<int>(C, 4);
+    TD_HIP(hipMemset(C->d_iflag, 0, 4 * sizeof(int)));
+    C->d_gbar = dalloc<unsigned>(C, 4);
+    TD_HIP(hipMemset(C->d_gbar, 0, 4 * sizeof(unsigned)));
     TD_HIP(hipHostMalloc((void **)&C->h_iflag, 4 * sizeof(int), hipHostMallocDefault));
     if (const char *gb = std::getenv("TDBEM_GMRES_BLOCKS")) C->gmres_blocks = std::max(1, std::atoi(gb));
     C->d_scal = dalloc<double>(C, 64 * (size_t)C->nrhs);
@@ -323,10 +326,14 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
             PhaseScope ps(C->prof, TDBEM_PH_GMRES, s);
             const int maxit = std::max(1, C->cfg.gmres_maxit);
             if (C->nrhs == 1 && C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s)) {
-                TD_HIP(hipMemcpyAsync(C->h_iflag, C->d_iflag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+                TD_HIP(hipMemcpyAsync(C->h_iflag, C->d_iflag, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
                 TD_HIP(hipStreamSynchronize(s));
                 C->last_iters = C->h_iflag[0];
                 ok = C->h_iflag[1] != 0;
+                if (C->h_iflag[2] != 0) {
+                    TD_HIP(hipMemset(C->d_gbar, 0, 4 * sizeof(unsigned)));
+                    throw Error{TDBEM_EHIP, "device solve: a grid barrier wait timed out"};
+                }
             } else {
                 C->last_iters = gmres_solve(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, &ok, s);
             }

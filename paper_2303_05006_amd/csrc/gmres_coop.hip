@@ -8,17 +8,16 @@
 // them in the same fixed order, so all blocks hold bitwise-identical scalars
 // and take identical branches: every barrier is reached by every block, and
 // the loop trip counts are bounded by the iteration cap.
-#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include "tdbem_internal.h"
 
-namespace cg = cooperative_groups;
 
 namespace tdbem {
 
 static constexpr int GM_MAXV = 33;      // Krylov vectors per restart cycle (m + 1) plus one self product
 static constexpr int GM_THREADS = 1024;
+static constexpr int GM_MAXBLK = 256;   // blocks of the cooperative solve at most
 
 struct GmresArgs {
     int ne, m, maxit;
@@ -31,8 +30,39 @@ struct GmresArgs {
     double *V;        // [(m+1)][ne]
     double *w0, *w1;  // ping-pong work vectors [ne]
     double *part;     // [nblk][GM_MAXV]
-    int *out;         // [0] iterations, [1] converged
+    int *out;         // [0] iterations, [1] converged, [2] a barrier wait timed out
+    unsigned *bar;    // [0] arrivals, [1] generation (device memory, arrivals zero between launches)
 };
+
+// Grid barrier of the cooperative launch (every block is resident): one
+// arrival counter and a generation word at device scope.  The last block to
+// arrive resets the counter and advances the generation; the others wait for
+// the generation to change.  The wait is bounded: after about a second it gives
+// up and flags out[2], so the kernel always completes (the host then reports
+// the failure).  Only thread 0 of a block touches the words.
+__device__ __forceinline__ void grid_barrier(const GmresArgs &A) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned g = __hip_atomic_load(&A.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned n = __hip_atomic_fetch_add(&A.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (n == gridDim.x - 1) {
+            __hip_atomic_store(&A.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&A.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            unsigned spins = 0;
+            while (__hip_atomic_load(&A.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > (1u << 24)) {
+                    A.out[2] = 1;
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
 
 // per-thread partial sums of <V_j, w> for j < nv over this block's rows,
 // reduced over the block into part[round parity][blk][j].  The two buffers
@@ -63,10 +93,11 @@ __device__ void block_dots(const GmresArgs &A, int rnd, int nv, const double *Vb
 // thread (j, b) loads part[b][j], then 64-lane groups reduce over b
 __device__ void grid_reduce(const GmresArgs &A, int rnd, int nv, double *dst) {
     const double *part = A.part + (size_t)(rnd & 1) * gridDim.x * GM_MAXV;
-    const int nb = gridDim.x;                       // <= 64 (launch-checked)
+    const int nb = gridDim.x;                       // <= GM_MAXBLK (launch-checked)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j = wave; j < nv; j += GM_THREADS / 64) {
-        double v = lane < nb ? part[(size_t)lane * GM_MAXV + j] : 0.0;
+        double v = 0.0;
+        for (int b = lane; b < nb; b += 64) v += part[(size_t)b * GM_MAXV + j];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if (lane == 0) dst[j] = v;
     }
@@ -104,18 +135,18 @@ __device__ void block_spmv(const int *ptr, const int *col, const double *a, cons
 }
 
 __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
-    cg::grid_group grid = cg::this_grid();
     __shared__ double red[(GM_THREADS / 64) * GM_MAXV];
     __shared__ double h1[GM_MAXV], h2[GM_MAXV], sc[4];
     __shared__ double H[GM_MAXV * GM_MAXV], cs[GM_MAXV], sn[GM_MAXV], gv[GM_MAXV + 1], y[GM_MAXV];
     const int ne = A.ne, m = A.m;
     const int nb = gridDim.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.out[2] = 0;
     const int r0 = (int)((int64_t)ne * blockIdx.x / nb), r1 = (int)((int64_t)ne * (blockIdx.x + 1) / nb);
     const size_t vs = (size_t)ne;
     int rnd = 0;
     // ||b||
     block_dots(A, rnd, 1, A.b, vs, A.b, r0, r1, red);
-    grid.sync();
+    grid_barrier(A);
     grid_reduce(A, rnd++, 1, sc);
     const double bn = sqrt(sc[0]);
     int total = 0;
@@ -125,7 +156,7 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
         block_spmv(A.ptr, A.col, A.val, A.x, 1.0, A.b, A.V, r0, r1);
         __syncthreads();
         block_dots(A, rnd, 1, A.V, vs, A.V, r0, r1, red);
-        grid.sync();
+        grid_barrier(A);
         grid_reduce(A, rnd++, 1, sc);
         const double beta = sqrt(sc[0]);
         if (beta <= A.rtol * bn || bn == 0.0) { conv = true; break; }
@@ -136,7 +167,7 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
             for (int q = 0; q <= m; ++q) gv[q] = 0.0;
             gv[0] = beta;
         }
-        grid.sync();   // V_0 complete before any block's SpMV
+        grid_barrier(A);   // V_0 complete before any block's SpMV
         int k = 0, kused = 0;
         double hscale = 1.0;            // 1/h_{k,k-1}: V_k = w_prev * hscale
         double *wprev = nullptr;
@@ -155,7 +186,7 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
             // |w - V h|^2 = |w|^2 - |h|^2 unless cancellation (DGKS criterion
             // |w - V h|^2 < |w|^2 / 2), in which case a second pass is made
             block_dots(A, rnd, k + 1, A.V, vs, w, r0, r1, red, true);
-            grid.sync();
+            grid_barrier(A);
             grid_reduce(A, rnd++, k + 2, h1);
             for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) {
                 double s = w[i];
@@ -173,7 +204,7 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
             __syncthreads();
             if (sc[3] != 0.0) {
                 block_dots(A, rnd, k + 1, A.V, vs, w, r0, r1, red, true);
-                grid.sync();
+                grid_barrier(A);
                 grid_reduce(A, rnd++, k + 2, h2);
                 for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) {
                     double s = w[i];
@@ -231,7 +262,7 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
             for (int j = 0; j < kused; ++j) s += y[j] * A.V[(size_t)j * vs + i];
             A.x[i] += A.dinv[i] * s;
         }
-        grid.sync();   // x complete before the next residual
+        grid_barrier(A);   // x complete before the next residual
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         A.out[0] = total;
@@ -251,7 +282,7 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
     TD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_gmres_coop, GM_THREADS, 0));
     int ncu = 0;
     TD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int nblk = std::min(std::min(C->gmres_blocks, 64), per_cu * ncu);
+    int nblk = std::min(std::min(C->gmres_blocks, GM_MAXBLK), per_cu * ncu);
     if (nblk < 1) return false;
     const int m = std::min(GM_MAXV - 1, std::max(1, maxit));
     double *V = C->d_work;
@@ -265,6 +296,7 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
     A.w1 = A.w0 + vs;
     A.part = A.w1 + vs;
     A.out = C->d_iflag;
+    A.bar = C->d_gbar;
     void *args[] = {&A};
     TD_HIP(hipLaunchCooperativeKernel((const void *)k_gmres_coop, dim3(nblk), dim3(GM_THREADS), args, 0, s));
     return true;

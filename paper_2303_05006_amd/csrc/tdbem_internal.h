@@ -158,6 +158,7 @@ struct tdbem_ctx {
     double *d_tmp = nullptr;        // [ne][nrhs] scratch (canonical order io)
     int *d_iflag = nullptr;         // device solver status: iterations, converged
     int *h_iflag = nullptr;         // pinned host mirror
+    unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve
     int gmres_blocks = 64;          // blocks of the cooperative solve
     bool use_coop = true;           // device-resident solve for one right-hand side
 
