@@ -67,7 +67,7 @@ void launch_gather_vals(const double *val, const int64_t *idx, int64_t n, double
 int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, bool *ok, hipStream_t s);
 size_t gmres_work_doubles(const tdbem_ctx *C, int maxit);
 bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s);
-size_t gmres_coop_work_doubles(int ne);
+size_t gmres_coop_work_doubles(int ne, int nrhs);
 
 static GeoDev geo(const tdbem_ctx *C) {
     return GeoDev{C->d_xyz, C->d_tri, C->d_area, C->d_nrm, C->d_qpt, C->d_etri, C->d_efree, C->d_elen,
@@ -282,12 +282,12 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_x = dalloc<double>(C, nv);
     C->d_tmp = dalloc<double>(C, nv);
     C->d_work = dalloc<double>(C, std::max(gmres_work_doubles(C, std::max(1, cfg->gmres_maxit)),
-                                           gmres_coop_work_doubles(ne)));
-    C->d_iflag = dalloc<int>(C, 4);
-    TD_HIP(hipMemset(C->d_iflag, 0, 4 * sizeof(int)));
-    C->d_gbar = dalloc<unsigned>(C, 4);
-    TD_HIP(hipMemset(C->d_gbar, 0, 4 * sizeof(unsigned)));
-    TD_HIP(hipHostMalloc((void **)&C->h_iflag, 4 * sizeof(int), hipHostMallocDefault));
+                                           gmres_coop_work_doubles(ne, C->nrhs)));
+    C->d_iflag = dalloc<int>(C, 4 * (size_t)C->nrhs);
+    TD_HIP(hipMemset(C->d_iflag, 0, 4 * (size_t)C->nrhs * sizeof(int)));
+    C->d_gbar = dalloc<unsigned>(C, 4 * (size_t)C->nrhs);
+    TD_HIP(hipMemset(C->d_gbar, 0, 4 * (size_t)C->nrhs * sizeof(unsigned)));
+    TD_HIP(hipHostMalloc((void **)&C->h_iflag, 4 * (size_t)C->nrhs * sizeof(int), hipHostMallocDefault));
     if (const char *gb = std::getenv("TDBEM_GMRES_BLOCKS")) C->gmres_blocks = std::max(1, std::atoi(gb));
     C->d_scal = dalloc<double>(C, 64 * (size_t)C->nrhs);
     C->d_pulse = dalloc<double>(C, 11 * (size_t)C->nrhs);
@@ -325,13 +325,20 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
         {
             PhaseScope ps(C->prof, TDBEM_PH_GMRES, s);
             const int maxit = std::max(1, C->cfg.gmres_maxit);
-            if (C->nrhs == 1 && C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s)) {
-                TD_HIP(hipMemcpyAsync(C->h_iflag, C->d_iflag, 3 * sizeof(int), hipMemcpyDeviceToHost, s));
+            if (C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s)) {
+                const size_t nf = 4 * (size_t)C->nrhs;
+                TD_HIP(hipMemcpyAsync(C->h_iflag, C->d_iflag, nf * sizeof(int), hipMemcpyDeviceToHost, s));
                 TD_HIP(hipStreamSynchronize(s));
-                C->last_iters = C->h_iflag[0];
-                ok = C->h_iflag[1] != 0;
-                if (C->h_iflag[2] != 0) {
-                    TD_HIP(hipMemset(C->d_gbar, 0, 4 * sizeof(unsigned)));
+                int its = 0;
+                bool timeout = false;
+                for (int r = 0; r < C->nrhs; ++r) {
+                    its = std::max(its, C->h_iflag[4 * r]);
+                    ok = ok && C->h_iflag[4 * r + 1] != 0;
+                    timeout = timeout || C->h_iflag[4 * r + 2] != 0;
+                }
+                C->last_iters = its;
+                if (timeout) {
+                    TD_HIP(hipMemset(C->d_gbar, 0, nf * sizeof(unsigned)));
                     throw Error{TDBEM_EHIP, "device solve: a grid barrier wait timed out"};
                 }
             } else {

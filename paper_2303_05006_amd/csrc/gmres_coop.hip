@@ -1,13 +1,15 @@
-// Device-resident restarted GMRES for Z0 x = b (one right-hand side), Section 2.5.
+// Device-resident restarted GMRES for Z0 x = b, Section 2.5.
 //
-// One cooperative launch of a few large blocks runs the whole solve: right
-// Jacobi preconditioning, Arnoldi with classical Gram-Schmidt applied twice,
-// Givens rotations and the restart logic.  Grid-wide barriers separate the
-// phases that read other blocks' rows (SpMV) or other blocks' partial sums
-// (dot products).  Partial sums are written per block and every block reduces
-// them in the same fixed order, so all blocks hold bitwise-identical scalars
-// and take identical branches: every barrier is reached by every block, and
-// the loop trip counts are bounded by the iteration cap.
+// One cooperative launch runs whole solves: right Jacobi preconditioning,
+// Arnoldi with classical Gram-Schmidt applied twice, Givens rotations and the
+// restart logic.  blockIdx.y selects an independent system (one right-hand
+// side, its vectors contiguous); the gridDim.x blocks of a system split its
+// rows.  Grid-wide barriers among a system's blocks separate the phases that
+// read other blocks' rows (SpMV) or other blocks' partial sums (dot products).
+// Partial sums are written per block and every block reduces them in the same
+// fixed order, so all blocks of a system hold bitwise-identical scalars and
+// take identical branches: every barrier is reached by every block, and the
+// loop trip counts are bounded by the iteration cap.
 #include <hip/hip_runtime.h>
 
 #include "tdbem_internal.h"
@@ -29,9 +31,12 @@ struct GmresArgs {
     double *x;
     double *V;        // [(m+1)][ne]
     double *w0, *w1;  // ping-pong work vectors [ne]
-    double *part;     // [nblk][GM_MAXV]
+    double *part;     // [2][nblk][GM_MAXV]
     int *out;         // [0] iterations, [1] converged, [2] a barrier wait timed out
     unsigned *bar;    // [0] arrivals, [1] generation (device memory, arrivals zero between launches)
+    // per-system strides for blockIdx.y: b and x advance by ne, V (and the
+    // w0, w1, part behind it) by sys_ws doubles, out and bar by 4
+    size_t sys_ws;
 };
 
 // Grid barrier of the cooperative launch (every block is resident): one
@@ -42,6 +47,7 @@ struct GmresArgs {
 // the failure).  Only thread 0 of a block touches the words.
 __device__ __forceinline__ void grid_barrier(const GmresArgs &A) {
     __syncthreads();
+    if (gridDim.x == 1) return;       // a one-block system: the block barrier suffices
     if (threadIdx.x == 0) {
         __threadfence();
         const unsigned g = __hip_atomic_load(&A.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -134,7 +140,19 @@ __device__ void block_spmv(const int *ptr, const int *col, const double *a, cons
     }
 }
 
-__global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
+__global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
+    GmresArgs A = Ain;
+    {
+        const size_t sys = blockIdx.y;
+        A.b += sys * (size_t)A.ne;
+        A.x += sys * (size_t)A.ne;
+        A.V += sys * A.sys_ws;
+        A.w0 += sys * A.sys_ws;
+        A.w1 += sys * A.sys_ws;
+        A.part += sys * A.sys_ws;
+        A.out += 4 * sys;
+        A.bar += 4 * sys;
+    }
     __shared__ double red[(GM_THREADS / 64) * GM_MAXV];
     __shared__ double h1[GM_MAXV], h2[GM_MAXV], sc[4];
     __shared__ double H[GM_MAXV * GM_MAXV], cs[GM_MAXV], sn[GM_MAXV], gv[GM_MAXV + 1], y[GM_MAXV];
@@ -173,6 +191,9 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
         double *wprev = nullptr;
         for (; k < m && total < A.maxit; ++k) {
             ++total;
+            // every block's rows of the previous w are final (the Gram-Schmidt
+            // update of iteration k-1 follows that iteration's last barrier)
+            if (k > 0) grid_barrier(A);
             double *w = (k & 1) ? A.w1 : A.w0;
             // w = A Dinv V_k, with V_k = wprev * hscale for k >= 1 (rows of other blocks)
             if (k == 0) {
@@ -270,8 +291,35 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs A) {
     }
 }
 
-// Launch the cooperative solve; returns false if the device cannot co-schedule
-// the grid (the caller then uses the host-driven solver).
+// dst[c][r] = src[r][c] for a rows x cols matrix of doubles, 32 x 32 tiles through LDS
+__global__ void k_transpose(int rows, int cols, const double *__restrict__ src, double *__restrict__ dst) {
+    __shared__ double t[32][33];
+    const int tiles_r = (rows + 31) / 32;
+    const int r0 = (int)(blockIdx.x % tiles_r) * 32, c0 = (int)(blockIdx.x / tiles_r) * 32;
+    for (int j = threadIdx.y; j < 32; j += 8) {
+        const int r = r0 + j, c = c0 + threadIdx.x;
+        if (r < rows && c < cols) t[j][threadIdx.x] = src[(size_t)r * cols + c];
+    }
+    __syncthreads();
+    for (int j = threadIdx.y; j < 32; j += 8) {
+        const int c = c0 + j, r = r0 + threadIdx.x;
+        if (r < rows && c < cols) dst[(size_t)c * rows + r] = t[threadIdx.x][j];
+    }
+}
+
+static void transpose(int rows, int cols, const double *src, double *dst, hipStream_t s) {
+    const unsigned tiles = (unsigned)((rows + 31) / 32) * (unsigned)((cols + 31) / 32);
+    hipLaunchKernelGGL(k_transpose, dim3(tiles), dim3(32, 8), 0, s, rows, cols, src, dst);
+}
+
+static size_t sys_work(int ne) { return (size_t)(GM_MAXV + 2) * ne + (size_t)2 * GM_MAXBLK * GM_MAXV; }
+
+// Launch the cooperative solves of every right-hand side ([ne][nrhs] vectors b
+// and x; x holds the initial guess on entry).  A single system takes
+// C->gmres_blocks blocks; several systems share the resident blocks, at least
+// one each, and are launched in groups when they do not all fit.  The status
+// words of system r are C->d_iflag[4r..4r+2].  Returns false if the device
+// cannot co-schedule the grid (the caller then uses the host-driven solver).
 bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s) {
     int dev = 0;
     TD_HIP(hipGetDevice(&dev));
@@ -282,28 +330,48 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
     TD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_gmres_coop, GM_THREADS, 0));
     int ncu = 0;
     TD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-    int nblk = std::min(std::min(C->gmres_blocks, GM_MAXBLK), per_cu * ncu);
-    if (nblk < 1) return false;
+    const int resident = per_cu * ncu;
+    const int nr = C->nrhs, ne = C->ne;
+    const int cap = std::min(C->gmres_blocks, GM_MAXBLK);
+    int nbx = nr == 1 ? std::min(cap, resident) : std::max(1, std::min(cap, resident / nr));
+    if (nbx < 1 || resident < 1) return false;
+    const int per_launch = std::max(1, resident / nbx);
     const int m = std::min(GM_MAXV - 1, std::max(1, maxit));
-    double *V = C->d_work;
-    size_t vs = (size_t)C->ne;
+    double *work = C->d_work;
+    const double *bs = b;
+    double *xs = x;
+    if (nr > 1) {                       // systems contiguous: [nrhs][ne]
+        double *bt = work, *xt = work + (size_t)ne * nr;
+        work = xt + (size_t)ne * nr;
+        transpose(ne, nr, b, bt, s);
+        transpose(ne, nr, x, xt, s);
+        bs = bt;
+        xs = xt;
+    }
     GmresArgs A;
-    A.ne = C->ne; A.m = m; A.maxit = maxit; A.rtol = rtol;
+    A.ne = ne; A.m = m; A.maxit = maxit; A.rtol = rtol;
     A.ptr = C->d_z0_ptr; A.col = C->d_z0_col; A.val = C->d_z0_val; A.dinv = C->d_z0_dinv; A.vald = C->d_z0_vald;
-    A.b = b; A.x = x;
-    A.V = V;
-    A.w0 = V + (size_t)(m + 1) * vs;
-    A.w1 = A.w0 + vs;
-    A.part = A.w1 + vs;
-    A.out = C->d_iflag;
-    A.bar = C->d_gbar;
-    void *args[] = {&A};
-    TD_HIP(hipLaunchCooperativeKernel((const void *)k_gmres_coop, dim3(nblk), dim3(GM_THREADS), args, 0, s));
+    A.sys_ws = sys_work(ne);
+    for (int r0 = 0; r0 < nr; r0 += per_launch) {
+        const int cnt = std::min(per_launch, nr - r0);
+        A.b = bs + (size_t)r0 * ne;
+        A.x = xs + (size_t)r0 * ne;
+        A.V = work + (size_t)r0 * A.sys_ws;
+        A.w0 = A.V + (size_t)(m + 1) * ne;
+        A.w1 = A.w0 + ne;
+        A.part = A.w1 + ne;
+        A.out = C->d_iflag + 4 * r0;
+        A.bar = C->d_gbar + 4 * r0;
+        void *args[] = {&A};
+        TD_HIP(hipLaunchCooperativeKernel((const void *)k_gmres_coop, dim3(nbx, cnt), dim3(GM_THREADS), args, 0, s));
+    }
+    if (nr > 1) transpose(nr, ne, xs, x, s);
+    TD_HIP(hipGetLastError());
     return true;
 }
 
-size_t gmres_coop_work_doubles(int ne) {
-    return (size_t)(GM_MAXV + 2) * ne + (size_t)2 * 4096 * GM_MAXV;
+size_t gmres_coop_work_doubles(int ne, int nrhs) {
+    return (size_t)nrhs * sys_work(ne) + (nrhs > 1 ? (size_t)2 * ne * nrhs : 0);
 }
 
 }  // namespace tdbem

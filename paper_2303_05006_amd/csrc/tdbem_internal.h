@@ -156,11 +156,11 @@ struct tdbem_ctx {
     double *h_scal = nullptr;       // pinned host mirror
     double *d_pulse = nullptr;      // [nrhs][11]
     double *d_tmp = nullptr;        // [ne][nrhs] scratch (canonical order io)
-    int *d_iflag = nullptr;         // device solver status: iterations, converged
+    int *d_iflag = nullptr;         // device solver status per rhs: iterations, converged, barrier timeout
     int *h_iflag = nullptr;         // pinned host mirror
-    unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve
+    unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve, 4 per rhs
     int gmres_blocks = 64;          // blocks of the cooperative solve
-    bool use_coop = true;           // device-resident solve for one right-hand side
+    bool use_coop = true;           // device-resident solve
 
     // host copies of the coefficient pair structure (leaf order, sorted by row)
     std::vector<int> hp_i, hp_j, hp_lo, hp_hi;
