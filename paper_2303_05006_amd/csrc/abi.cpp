@@ -285,8 +285,8 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
                                            gmres_coop_work_doubles(ne, C->nrhs)));
     C->d_iflag = dalloc<int>(C, 4 * (size_t)C->nrhs);
     TD_HIP(hipMemset(C->d_iflag, 0, 4 * (size_t)C->nrhs * sizeof(int)));
-    C->d_gbar = dalloc<unsigned>(C, 4 * (size_t)C->nrhs);
-    TD_HIP(hipMemset(C->d_gbar, 0, 4 * (size_t)C->nrhs * sizeof(unsigned)));
+    C->d_gbar = dalloc<unsigned>(C, (size_t)GMRES_BAR_WORDS * C->nrhs);
+    TD_HIP(hipMemset(C->d_gbar, 0, (size_t)GMRES_BAR_WORDS * C->nrhs * sizeof(unsigned)));
     TD_HIP(hipHostMalloc((void **)&C->h_iflag, 4 * (size_t)C->nrhs * sizeof(int), hipHostMallocDefault));
     if (const char *gb = std::getenv("TDBEM_GMRES_BLOCKS")) C->gmres_blocks = std::max(1, std::atoi(gb));
     C->d_scal = dalloc<double>(C, 64 * (size_t)C->nrhs);
@@ -338,7 +338,7 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
                 }
                 C->last_iters = its;
                 if (timeout) {
-                    TD_HIP(hipMemset(C->d_gbar, 0, nf * sizeof(unsigned)));
+                    TD_HIP(hipMemset(C->d_gbar, 0, (size_t)GMRES_BAR_WORDS * C->nrhs * sizeof(unsigned)));
                     throw Error{TDBEM_EHIP, "device solve: a grid barrier wait timed out"};
                 }
             } else {

@@ -33,31 +33,38 @@ struct GmresArgs {
     double *w0, *w1;  // ping-pong work vectors [ne]
     double *part;     // [2][nblk][GM_MAXV]
     int *out;         // [0] iterations, [1] converged, [2] a barrier wait timed out
-    unsigned *bar;    // [0] arrivals, [1] generation (device memory, arrivals zero between launches)
+    unsigned *bar;    // barrier words (device memory, counters zero between launches)
     // per-system strides for blockIdx.y: b and x advance by ne, V (and the
-    // w0, w1, part behind it) by sys_ws doubles, out and bar by 4
+    // w0, w1, part behind it) by sys_ws doubles, out by 4, bar by GMRES_BAR_WORDS
     size_t sys_ws;
 };
 
 // Grid barrier of the cooperative launch (every block is resident): one
-// arrival counter and a generation word at device scope.  The last block to
-// arrive resets the counter and advances the generation; the others wait for
-// the generation to change.  The wait is bounded: after about a second it gives
-// up and flags out[2], so the kernel always completes (the host then reports
-// the failure).  Only thread 0 of a block touches the words.
+// arrival counter and a generation word at device scope, each in a 4 KB page of
+// its own (bar[0] and bar[GM_BAR_SLOT]), so that the arrivals do not queue
+// behind the polling of the generation (measured: a tenth of the solve time
+// against both words in one cache line; a two-level arrival tree or one
+// generation copy per XCD group were slower).  The last block to arrive resets
+// the counter and advances the generation; the others wait for the generation
+// to change.  The wait is bounded: after about a second it gives up and flags
+// out[2], so the kernel always completes (the host then reports the failure).
+// Only thread 0 of a block touches the words.
+static constexpr int GM_BAR_SLOT = 1024;
+static_assert(2 * GM_BAR_SLOT <= GMRES_BAR_WORDS, "barrier words per system");
+
 __device__ __forceinline__ void grid_barrier(const GmresArgs &A) {
     __syncthreads();
     if (gridDim.x == 1) return;       // a one-block system: the block barrier suffices
     if (threadIdx.x == 0) {
         __threadfence();
-        const unsigned g = __hip_atomic_load(&A.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned n = __hip_atomic_fetch_add(&A.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (n == gridDim.x - 1) {
-            __hip_atomic_store(&A.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&A.bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned *cnt = A.bar, *gen = A.bar + GM_BAR_SLOT;
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             unsigned spins = 0;
-            while (__hip_atomic_load(&A.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(2);
                 if (++spins > (1u << 24)) {
                     A.out[2] = 1;
@@ -110,32 +117,101 @@ __device__ void grid_reduce(const GmresArgs &A, int rnd, int nv, double *dst) {
     __syncthreads();
 }
 
-// y_i = sum_q a_q v[col_q] (+ scale) for the block's rows; 32 lanes per row so that
-// the row's loads are independent, shuffle reduction within the half-wave.
-// mode 0: y = A v;  mode 1: y = b - A v
+// y_i = sum_q a_q v[col_q] for the block's rows, 32 lanes per row (lane l takes
+// entries l, l + 32, ... of the row), shuffle reduction within the half-wave.
+// The first 32 entries of GM_GU rows per half-wave are loaded without a loop, so
+// that all their loads are in flight together; longer rows finish in a loop.
+// mode: y = b - A v if b is given, else y = vscale * A v
+static constexpr int GM_GU = 4;
 __device__ void block_spmv(const int *ptr, const int *col, const double *a, const double *v, double vscale,
                            const double *b, double *y, int r0, int r1) {
     const int hl = threadIdx.x & 31, hw = threadIdx.x >> 5;
     const int NH = GM_THREADS / 32;
-    // four rows per half-wave in flight: all loads issued before the reductions
-    for (int i0 = r0; i0 < r1; i0 += 4 * NH) {
-        int ii[4], q0[4], q1[4];
-        double s[4];
+    for (int i0 = r0; i0 < r1; i0 += GM_GU * NH) {
+        int ii[GM_GU], q0[GM_GU], q1[GM_GU], cq[GM_GU];
+        double aq[GM_GU], s[GM_GU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < GM_GU; ++u) {
             ii[u] = i0 + u * NH + hw;
-            bool ok = ii[u] < r1;
+            const bool ok = ii[u] < r1;
             q0[u] = ok ? ptr[ii[u]] : 0;
             q1[u] = ok ? ptr[ii[u] + 1] : 0;
-            s[u] = 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            for (int q = q0[u] + hl; q < q1[u]; q += 32) s[u] += a[q] * v[col[q]];
+        for (int u = 0; u < GM_GU; ++u) {
+            const int q = q0[u] + hl;
+            const bool ok = q < q1[u];
+            cq[u] = ok ? col[q] : -1;
+            aq[u] = ok ? a[q] : 0.0;
+        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < GM_GU; ++u) s[u] = cq[u] >= 0 ? aq[u] * v[cq[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < GM_GU; ++u)
+            for (int q = q0[u] + 32 + hl; q < q1[u]; q += 32) s[u] += a[q] * v[col[q]];
+#pragma unroll
+        for (int u = 0; u < GM_GU; ++u) {
             for (int o = 16; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, 32);
             if (hl == 0 && ii[u] < r1) y[ii[u]] = b ? b[ii[u]] - s[u] : s[u] * vscale;
+        }
+    }
+}
+
+// The preconditioned operator's rows of a block kept in LDS for the whole
+// solve: half-wave hw owns rows r0 + hw + 32 u (u < nu <= GM_RU), lane l the
+// row's entry l, column at rc[u][thread] (-1: none) and value at ra[u][thread].
+// Rows with more than 32 entries have bit u set in the lane's `tail` mask and
+// read the rest from memory.  Used when the block has at most 32 GM_RU rows.
+static constexpr int GM_RU = 12;
+static constexpr int GM_RC = 4;     // slots per chunk: gathers of a chunk in flight together
+static_assert(GM_RU % GM_RC == 0, "chunks tile the slots");
+
+__device__ __forceinline__ unsigned load_lds_rows(int *rc, double *ra, const int *ptr, const int *col, const double *a,
+                                                  int r0, int r1) {
+    const int hl = threadIdx.x & 31, hw = threadIdx.x >> 5;
+    unsigned tail = 0;
+    for (int u = 0; u < GM_RU; ++u) {
+        const int i = r0 + hw + 32 * u;
+        int q0 = 0, q1 = 0;
+        if (i < r1) { q0 = ptr[i]; q1 = ptr[i + 1]; }
+        const int q = q0 + hl;
+        rc[u * GM_THREADS + threadIdx.x] = q < q1 ? col[q] : -1;
+        ra[u * GM_THREADS + threadIdx.x] = q < q1 ? a[q] : 0.0;
+        if (q1 - q0 > 32) tail |= 1u << u;
+    }
+    return tail;
+}
+
+// y_i = vscale * sum_q a_q v[col_q] with the rows in LDS (nu slots in use)
+__device__ __forceinline__ void block_spmv_lds(const int *rc, const double *ra, unsigned tail, int nu,
+                                               const int *ptr, const int *col, const double *a, const double *v,
+                                               double vscale, double *y, int r0, int r1) {
+    const int hl = threadIdx.x & 31, hw = threadIdx.x >> 5;
+    for (int u0 = 0; u0 < nu; u0 += GM_RC) {
+        int c[GM_RC];
+        double s[GM_RC];
+#pragma unroll
+        for (int u = 0; u < GM_RC; ++u) c[u] = rc[(u0 + u) * GM_THREADS + threadIdx.x];
+#pragma unroll
+        for (int u = 0; u < GM_RC; ++u) s[u] = c[u] >= 0 ? v[c[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < GM_RC; ++u) s[u] *= ra[(u0 + u) * GM_THREADS + threadIdx.x];
+        if ((tail >> u0) & ((1u << GM_RC) - 1u)) {
+#pragma unroll
+            for (int u = 0; u < GM_RC; ++u) {
+                if (!((tail >> (u0 + u)) & 1u)) continue;
+                const int i = r0 + hw + 32 * (u0 + u);
+                const int q1 = ptr[i + 1];
+                double t = 0.0;
+                for (int q = ptr[i] + 32 + hl; q < q1; q += 32) t += a[q] * v[col[q]];
+                s[u] += t;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GM_RC; ++u) {
+            for (int o = 16; o > 0; o >>= 1) s[u] += __shfl_xor(s[u], o, 32);
+            const int i = r0 + hw + 32 * (u0 + u);
+            if (hl == 0 && i < r1) y[i] = s[u] * vscale;
         }
     }
 }
@@ -151,7 +227,7 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
         A.w1 += sys * A.sys_ws;
         A.part += sys * A.sys_ws;
         A.out += 4 * sys;
-        A.bar += 4 * sys;
+        A.bar += (size_t)GMRES_BAR_WORDS * sys;
     }
     __shared__ double red[(GM_THREADS / 64) * GM_MAXV];
     __shared__ double h1[GM_MAXV], h2[GM_MAXV], sc[4];
@@ -161,6 +237,11 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
     if (blockIdx.x == 0 && threadIdx.x == 0) A.out[2] = 0;
     const int r0 = (int)((int64_t)ne * blockIdx.x / nb), r1 = (int)((int64_t)ne * (blockIdx.x + 1) / nb);
     const size_t vs = (size_t)ne;
+    const bool regs = r1 - r0 <= 32 * GM_RU;   // block-uniform
+    const int nu = (r1 - r0 + 31) / 32;
+    __shared__ int rc[GM_RU * GM_THREADS];
+    __shared__ double ra[GM_RU * GM_THREADS];
+    const unsigned tail = regs ? load_lds_rows(rc, ra, A.ptr, A.col, A.vald, r0, r1) : 0u;
     int rnd = 0;
     // ||b||
     block_dots(A, rnd, 1, A.b, vs, A.b, r0, r1, red);
@@ -197,15 +278,20 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
             double *w = (k & 1) ? A.w1 : A.w0;
             // w = A Dinv V_k, with V_k = wprev * hscale for k >= 1 (rows of other blocks)
             if (k == 0) {
-                block_spmv(A.ptr, A.col, A.vald, A.V, 1.0, nullptr, w, r0, r1);
+                if (regs) block_spmv_lds(rc, ra, tail, nu, A.ptr, A.col, A.vald, A.V, 1.0, w, r0, r1);
+                else block_spmv(A.ptr, A.col, A.vald, A.V, 1.0, nullptr, w, r0, r1);
             } else {
-                block_spmv(A.ptr, A.col, A.vald, wprev, hscale, nullptr, w, r0, r1);
+                if (regs) block_spmv_lds(rc, ra, tail, nu, A.ptr, A.col, A.vald, wprev, hscale, w, r0, r1);
+                else block_spmv(A.ptr, A.col, A.vald, wprev, hscale, nullptr, w, r0, r1);
                 for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) A.V[(size_t)k * vs + i] = wprev[i] * hscale;
             }
             __syncthreads();
             // Gram-Schmidt with the norm in the same reduction: h = V^T w and |w|^2;
             // |w - V h|^2 = |w|^2 - |h|^2 unless cancellation (DGKS criterion
-            // |w - V h|^2 < |w|^2 / 2), in which case a second pass is made
+            // |w - V h|^2 < |w|^2 / 2), in which case a second pass is made.
+            // (A looser threshold, a second pass only below 1e-4 |w|^2, let the
+            // least-squares residual estimate drift from the true residual at
+            // rtol 1e-12: 30 to 100 iterations per step where 11 to 13 suffice.)
             block_dots(A, rnd, k + 1, A.V, vs, w, r0, r1, red, true);
             grid_barrier(A);
             grid_reduce(A, rnd++, k + 2, h1);
@@ -315,9 +401,9 @@ static void transpose(int rows, int cols, const double *src, double *dst, hipStr
 static size_t sys_work(int ne) { return (size_t)(GM_MAXV + 2) * ne + (size_t)2 * GM_MAXBLK * GM_MAXV; }
 
 // Launch the cooperative solves of every right-hand side ([ne][nrhs] vectors b
-// and x; x holds the initial guess on entry).  A single system takes
-// C->gmres_blocks blocks; several systems share the resident blocks, at least
-// one each, and are launched in groups when they do not all fit.  The status
+// and x; x holds the initial guess on entry).  Several systems share the
+// resident blocks, at least one each, and are launched in groups when they do
+// not all fit.  The status
 // words of system r are C->d_iflag[4r..4r+2].  Returns false if the device
 // cannot co-schedule the grid (the caller then uses the host-driven solver).
 bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s) {
@@ -332,8 +418,15 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
     TD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     const int resident = per_cu * ncu;
     const int nr = C->nrhs, ne = C->ne;
-    const int cap = std::min(C->gmres_blocks, GM_MAXBLK);
-    int nbx = nr == 1 ? std::min(cap, resident) : std::max(1, std::min(cap, resident / nr));
+    // blocks per system: C->gmres_blocks if set; else for one system enough
+    // blocks (at least 64) to hold its rows in LDS, for several an equal share
+    const int cap = C->gmres_blocks > 0 ? std::min(C->gmres_blocks, GM_MAXBLK) : GM_MAXBLK;
+    int nbx;
+    if (nr == 1)
+        nbx = C->gmres_blocks > 0 ? cap : std::min(GM_MAXBLK, std::max(64, (ne + 32 * GM_RU - 1) / (32 * GM_RU)));
+    else
+        nbx = std::max(1, std::min(cap, resident / nr));
+    nbx = std::min(nbx, resident);
     if (nbx < 1 || resident < 1) return false;
     const int per_launch = std::max(1, resident / nbx);
     const int m = std::min(GM_MAXV - 1, std::max(1, maxit));
@@ -361,7 +454,7 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
         A.w1 = A.w0 + ne;
         A.part = A.w1 + ne;
         A.out = C->d_iflag + 4 * r0;
-        A.bar = C->d_gbar + 4 * r0;
+        A.bar = C->d_gbar + (size_t)GMRES_BAR_WORDS * r0;
         void *args[] = {&A};
         TD_HIP(hipLaunchCooperativeKernel((const void *)k_gmres_coop, dim3(nbx, cnt), dim3(GM_THREADS), args, 0, s));
     }

@@ -101,6 +101,9 @@ struct PhaseScope {
     ~PhaseScope() { if (P.on && e0) P.end(ph, s, e0); }
 };
 
+// words of grid-barrier state per system of the device solve (two 4 KB pages)
+constexpr int GMRES_BAR_WORDS = 2 * 1024;
+
 }  // namespace tdbem
 
 struct tdbem_ctx {
@@ -158,8 +161,8 @@ struct tdbem_ctx {
     double *d_tmp = nullptr;        // [ne][nrhs] scratch (canonical order io)
     int *d_iflag = nullptr;         // device solver status per rhs: iterations, converged, barrier timeout
     int *h_iflag = nullptr;         // pinned host mirror
-    unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve, 4 per rhs
-    int gmres_blocks = 64;          // blocks of the cooperative solve
+    unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve, GMRES_BAR_WORDS per rhs
+    int gmres_blocks = 0;           // blocks per system of the cooperative solve (0: automatic)
     bool use_coop = true;           // device-resident solve
 
     // host copies of the coefficient pair structure (leaf order, sorted by row)
