@@ -21,6 +21,7 @@ namespace tdbem {
 // number of pairs with a strip longer than l; off_l is its prefix sum.
 static constexpr int NEAR_LMAX = 512;
 static constexpr int NEAR_NU = 2;      // lag steps of 4 lags loaded together per chunk
+static constexpr int NEAR_NC = 1;      // 64-pair blocks per chunk
 
 // bf16 storage of near-field coefficients (BF16 form): round to nearest even on
 // the way in, exact widening on the way out; the sums stay FP64
@@ -62,21 +63,23 @@ __device__ __forceinline__ unsigned xcd_block() {
 }
 static unsigned grid8(uint64_t nb) { return (unsigned)((nb + 7) / 8 * 8); }
 
-template <typename VT, typename JT, int NU>
-__global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
+template <typename VT, typename JT, int NU, int NC>
+__global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
                                                    const int *__restrict__ nl, int L, const int *__restrict__ pj,
                                                    const int *__restrict__ pgl, const VT *__restrict__ val,
                                                    const JT *__restrict__ ring, int ring_mask, int alpha,
                                                    double *__restrict__ out) {
-    // One wavefront per target row.  The row's pairs are taken 64 at a time
-    // (a chunk): lane l loads the metadata of pair l of the chunk, and the
-    // next chunk's metadata is loaded while this one is summed, so no pass
-    // waits for it.  Within a chunk the lanes are 16 pairs x 4 consecutive
-    // lags (a current gather touches a short stretch of 16 ring rows, a
-    // coefficient load 16 consecutive values of one lag); the four groups of
-    // 16 pairs and NU lag steps of 4 lags are loaded together, 8 NU values per
-    // lane in flight, before any product is formed.  Longer strips take
-    // further rounds of 4 NU lags (the chunk's first pair is its longest).
+    // One wavefront per target row.  The row's pairs are taken 64 NC at a time
+    // (a chunk): lane l loads the metadata of pairs l, l + 64, ... of the
+    // chunk, and the next chunk's metadata is loaded while this one is summed,
+    // so no round waits for it.  Within a chunk the lanes are 16 pairs x 4
+    // consecutive lags (a current gather touches a short stretch of 16 ring
+    // rows, a coefficient load 16 consecutive values of one lag); the 4 NC
+    // groups of 16 pairs and NU lag steps of 4 lags are loaded together,
+    // 8 NC NU values per lane in flight, before any product is formed.  Longer
+    // strips take further rounds of 4 NU lags (the chunk's first pair is its
+    // longest: pairs are sorted by strip length).
+    constexpr int CH = 64 * NC, NG = 4 * NC;
     __shared__ int offs[4][NEAR_LMAX];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = (int)xcd_block() * 4 + wv;
@@ -88,31 +91,41 @@ __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict
     const int R = ring_mask + 1;
     const int sub = lane & 3, pg = lane >> 2;
     double acc = 0.0;
-    int mj = 0, mgl = 0;
-    if (lane < np) { mj = pj[pb + lane]; mgl = pgl[pb + lane]; }
-    for (int c0 = 0; c0 < np; c0 += 64) {
-        int nj = 0, ngl = 0;
-        if (c0 + 64 + lane < np) { nj = pj[pb + c0 + 64 + lane]; ngl = pgl[pb + c0 + 64 + lane]; }
-        const int cnt = min(64, np - c0);
-        const int lmax = __shfl(mgl, 0, 64) >> 16;
-        const JT *J[4];
-        int bq[4], len[4];
+    int mj[NC], mgl[NC];
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int q = 16 * g + pg;
-            const int j = __shfl(mj, q, 64), gl = __shfl(mgl, q, 64);
+    for (int h = 0; h < NC; ++h) {
+        const int p = 64 * h + lane;
+        mj[h] = p < np ? pj[pb + p] : 0;
+        mgl[h] = p < np ? pgl[pb + p] : 0;
+    }
+    for (int c0 = 0; c0 < np; c0 += CH) {
+        int nj[NC], ngl[NC];
+#pragma unroll
+        for (int h = 0; h < NC; ++h) {
+            const int p = c0 + CH + 64 * h + lane;
+            nj[h] = p < np ? pj[pb + p] : 0;
+            ngl[h] = p < np ? pgl[pb + p] : 0;
+        }
+        const int cnt = min(CH, np - c0);
+        const int lmax = __shfl(mgl[0], 0, 64) >> 16;
+        const JT *J[NG];
+        int bq[NG], len[NG];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const int q = 16 * g + pg;                    // pair of the chunk
+            const int j = __shfl(mj[g / 4], q & 63, 64), gl = __shfl(mgl[g / 4], q & 63, 64);
             J[g] = ring + (size_t)j * R;
             bq[g] = alpha - (gl & 0xffff);
             len[g] = q < cnt ? gl >> 16 : 0;
         }
         for (int lb = 0; lb < lmax; lb += 4 * NU) {
-            double a[4][NU], x[4][NU];
+            double a[NG][NU], x[NG][NU];
 #pragma unroll
             for (int t = 0; t < NU; ++t) {
                 const int l = lb + 4 * t + sub;
                 const int ol = l < L ? off[l] : 0;
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
+                for (int g = 0; g < NG; ++g) {
                     const bool ok = l < len[g];
                     a[g][t] = ok ? (double)v[ol + c0 + 16 * g + pg] : 0.0;
                     x[g][t] = ok ? (double)J[g][(bq[g] - l) & ring_mask] : 0.0;
@@ -121,10 +134,13 @@ __global__ void __launch_bounds__(256) k_near_jds1(int ne, const int *__restrict
 #pragma unroll
             for (int t = 0; t < NU; ++t)
 #pragma unroll
-                for (int g = 0; g < 4; ++g) acc += a[g][t] * x[g][t];
+                for (int g = 0; g < NG; ++g) acc += a[g][t] * x[g][t];
         }
-        mj = nj;
-        mgl = ngl;
+#pragma unroll
+        for (int h = 0; h < NC; ++h) {
+            mj[h] = nj[h];
+            mgl[h] = ngl[h];
+        }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) out[row] = acc;
@@ -196,7 +212,7 @@ template <typename VT, typename JT>
 static void launch_near_t(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
     if (C->nrhs == 1) {
         unsigned nb = grid8((C->ne + 3) / 4);
-        hipLaunchKernelGGL((k_near_jds1<VT, JT, NEAR_NU>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+        hipLaunchKernelGGL((k_near_jds1<VT, JT, NEAR_NU, NEAR_NC>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
                            C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
     } else {
         int ngrp = (C->nrhs + 63) / 64;
