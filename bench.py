@@ -186,6 +186,45 @@ def kernel_rooflines(info, ph, W, K, nr, prec_fp64, form):
     return roof, kernels
 
 
+def batched_runs(torch, tdbem, W, K, rtol, single_fp64_steps_per_s):
+    """64 incident fields (Fibonacci directions, seeded polarisations) marched
+    together: the plain FP64 form and the chosen form (FP32 near values and
+    M2L, learned initial guess), W + K steps each with the fields resident in
+    HBM, K timed; the chosen form's error is taken against the FP64 batch over
+    all W + K steps (the pulse crosses the sphere from about step 200)."""
+    from paper_2303_05006_amd.inputs import workload
+    w = workload("sphere20480x64", n_rhs=64)
+    nr = len(w.pulses)
+    last = W + K
+    out = {"workload": f"sphere20480x64: the same sphere, {nr} incident fields, steps {W + 1}..{last} timed",
+           "n_rhs": nr, "steps": K, "warmup": W}
+    trajs = {}
+    for key, form, guess in (("fp64", "fp64", "extrap"), ("chosen", "fp32", "learned")):
+        S, setup = make_solver(torch, tdbem, w, form, guess, rtol)
+        V = torch.zeros((last, nr, S.ne), dtype=torch.float64, device="cuda")
+        for a in range(1, last + 1):
+            S.incident(w.pulses, a, V[a - 1])
+        traj = torch.zeros((last, nr, S.ne), dtype=torch.float64, device="cuda")
+        el, iters = march(torch, S, V, W, K, traj)
+        ph = S.phase_times()
+        roof, _ = kernel_rooflines(S.info(), ph, W, K, nr, form == "fp64", form)
+        out[key] = {"form": form + (" + learned initial guess" if guess == "learned" else ""),
+                    "steps_per_s": K / el, "rhs_steps_per_s": nr * K / el, "ms_per_step": el / K * 1e3,
+                    "gmres_iters_mean": float(np.mean(iters)), "roofline": roof,
+                    "phase_ms": {k: v[0] for k, v in ph.items()}, "setup_s": setup}
+        trajs[key] = traj
+        S.close()
+        del V
+    a, b = trajs["chosen"], trajs["fp64"]
+    out["chosen"]["rel_l2_err_vs_fp64"] = float(((a - b) ** 2).sum().sqrt() / (b ** 2).sum().sqrt())
+    out["chosen"]["err_over_steps"] = f"1..{last}"
+    out["chosen"]["speedup_vs_fp64_batched"] = out["chosen"]["steps_per_s"] / out["fp64"]["steps_per_s"]
+    out["chosen"]["rhs_throughput_vs_fp64_single"] = out["chosen"]["rhs_steps_per_s"] / single_fp64_steps_per_s
+    del trajs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +238,10 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--guess", default="extrap", choices=["extrap", "learned"],
                     help="initial guess of the Z0 solve (learned: the committed network parameters)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched runs (64 incident fields, FP64 and FP32 + learned guess)")
+    ap.add_argument("--batched-steps", type=int, default=60)
+    ap.add_argument("--batched-warmup", type=int, default=240)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one 512 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -275,6 +318,8 @@ def main():
                          "phase_ms": {k: v[0] for k, v in ph2.items()},
                          "gmres_iters_mean": float(np.mean(iters2)), "setup_s": setup2}
         S2.close()
+    if chosen and not args.no_batched:
+        res["batched"] = batched_runs(torch, tdbem, args.batched_warmup, args.batched_steps, args.rtol, K / el)
     if args.copy_probe:
         res["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:

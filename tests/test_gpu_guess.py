@@ -309,3 +309,50 @@ def test_trained_guess_does_not_cost_iterations():
     print(f"GMRES iterations per step: extrapolation {res[tdbem.GUESS_EXTRAP]:.2f}, "
           f"learned {res[tdbem.GUESS_LEARNED]:.2f} (learned guess taken in {used} of {2 * 699} steps)")
     assert res[tdbem.GUESS_LEARNED] <= res[tdbem.GUESS_EXTRAP]
+
+
+@pytest.mark.parametrize("prec,tol", [(tdbem.FP64, 1e-9), (tdbem.FP32, 1e-5)])
+def test_learned_guess_batched_equals_single_runs(prec, tol):
+    """Three incident fields marched in one batch with the learned guess against
+    three single runs: the features, the network and the residual judge act
+    per right-hand side, so every column reaches the same solution (both solve
+    Z0 to 1e-12).  In FP64 the columns agree to the solver tolerance.  The FP32
+    form (the chosen configuration) evaluates its batched M2L with another
+    kernel and summation order than a single field, and the march amplifies
+    that FP32 rounding (6.6e-7 measured)."""
+    torch = _torch()
+    params = np.load(WEIGHTS)
+    v, f = icosphere(3)
+    dt = 0.04 / C0
+    pulses = [gaussian_pulse(150e6, 100e6, k=(np.sin(0.7 * i), np.cos(0.7 * i), 0.2)) for i in range(3)]
+    cfg = dict(dt=dt, mode=tdbem.MODE_IFMM, precision=prec, gmres_rtol=1e-12, gmres_maxit=200,
+               guess=tdbem.GUESS_LEARNED)
+    nt = 120
+    B = tdbem.Solver(v, f, tdbem.Config(n_rhs=3, **cfg))
+    B.guess_weights(params)
+    V = torch.zeros((3, B.ne), dtype=torch.float64, device="cuda")
+    J = torch.zeros((3, B.ne), dtype=torch.float64, device="cuda")
+    out = torch.zeros((nt - 1, 3, B.ne), dtype=torch.float64, device="cuda")
+    for a in range(1, nt):
+        B.incident(pulses, a, V)
+        B.step(V, J)
+        out[a - 1] = J
+    used_b = B.guess_used()
+    B.close()
+    S = tdbem.Solver(v, f, tdbem.Config(**cfg))
+    S.guess_weights(params)
+    for r, p in enumerate(pulses):
+        S.reset()
+        V1 = torch.zeros(S.ne, dtype=torch.float64, device="cuda")
+        J1 = torch.zeros(S.ne, dtype=torch.float64, device="cuda")
+        ref = torch.zeros((nt - 1, S.ne), dtype=torch.float64, device="cuda")
+        for a in range(1, nt):
+            S.incident([p], a, V1)
+            S.step(V1, J1)
+            ref[a - 1] = J1
+        rel = float(((out[:, r] - ref) ** 2).sum().sqrt() / (ref ** 2).sum().sqrt())
+        print(f"rhs {r}: batched vs single rel l2 {rel:.2e}")
+        assert rel < tol
+    S.close()
+    print(f"learned guess taken in {used_b} of {3 * (nt - 1)} (step, rhs) solves of the batch")
+    assert used_b > 0
