@@ -486,6 +486,12 @@ __global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int 
 // T is the arithmetic type of the operator and the products (FP64 form: double
 // with the f64 instruction; FP32 form: float with the f32 instruction); the
 // moments and the accumulated local expansions stay in FP64 in HBM.
+//
+// X sits in LDS column-major, X[column][k] with M2L_XS(T) values per column:
+// a lane's B operands of all 64 k-steps then lie within 2 KB of one address
+// (immediate offsets, no address arithmetic between the reads, so the reads can
+// run ahead of the products), and the padding (2 doubles or 4 floats) puts the
+// 16 columns x 4 k-rows of one read on distinct banks.
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -504,21 +510,35 @@ template <> struct Mma<float> {
 static constexpr int KTAB = 2401;          // 7^3 spatial differences x 7 time differences
 static constexpr int KTAB_MID = 1197;      // table index of a - b = (0, 0, 0), m - n = -3
 static constexpr int M2L_THREADS = 512;    // 8 wavefronts: 4 row blocks of 64 x 2 column halves
+template <typename T> struct M2lX { static constexpr int XS = NN + (sizeof(T) == 8 ? 2 : 4); };
 
 // operator table of one (offset, lag): tab[((d1 + 3) * 7 + d2 + 3) * 7 + d3 + 3) * 7 + w + 3] =
 // kernel at spatial lattice vector d - 3 off and time lattice 3 lag + w.
 // kind 0: dU/dt = 2c (c tau - r)_+ / r; kind 1: U = (c tau - r)_+^2 / r.
+// The distance r and 1 / r of the 343 spatial differences do not depend on the
+// lag: m2l_dist tabulates them once per block, and each lag's table is then a
+// multiply-add and a product per entry.  r stays FP64 (c tau - r cancels near
+// the light cone); 1 / r is kept in T (the FP32 form rounds the table to float
+// anyway, and two of its blocks then still fit one CU's LDS).
 template <typename T>
-__device__ void m2l_table(T *tab, int ox, int oy, int oz, int lag, int kind, double gs, double ds, double cgt,
-                          double c2) {
-    for (int e = threadIdx.x; e < KTAB; e += blockDim.x) {
-        const int w = e % 7 - 3, d = e / 7;
+__device__ void m2l_dist(double *rd, T *ird, int ox, int oy, int oz, double gs, double ds) {
+    for (int d = threadIdx.x; d < 343; d += blockDim.x) {
         const double v1 = gs * (d / 49 - 3) - ds * ox, v2 = gs * ((d / 7) % 7 - 3) - ds * oy,
                      v3 = gs * (d % 7 - 3) - ds * oz;
         const double r = sqrt(v1 * v1 + v2 * v2 + v3 * v3);
+        rd[d] = r;
+        ird[d] = (T)(r > 0.0 ? 1.0 / r : 0.0);
+    }
+}
+
+template <typename T>
+__device__ void m2l_table(T *tab, const double *rd, const T *ird, int lag, int kind, double cgt, double c2) {
+    for (int e = threadIdx.x; e < KTAB; e += blockDim.x) {
+        const int w = e % 7 - 3, d = e / 7;
+        const double r = rd[d];
         const double u = cgt * (3 * lag + w) - r;
         double kv = 0.0;
-        if (u > 0.0 && r > 0.0) kv = kind == 0 ? c2 * u / r : u * u / r;
+        if (u > 0.0 && r > 0.0) kv = kind == 0 ? c2 * u * (double)ird[d] : u * u * (double)ird[d];
         tab[e] = (T)kv;
     }
 }
@@ -535,27 +555,35 @@ __device__ __forceinline__ void m2l_row_base(int (&base)[4], int wr, int lane) {
     }
 }
 
-// acc (this wave's 64 rows x 32 columns) += K X for the table in LDS
+// acc (this wave's 64 rows x 32 columns) += K X for the table in LDS.  The
+// operands of k-step ks + 1 are read from LDS before the 8 products of k-step
+// ks are issued (scheduling barriers keep the two apart), so each read has a
+// whole k-step of matrix-core work to complete in.
 template <typename T>
-__device__ __forceinline__ void m2l_apply(typename Mma<T>::acc_t (&acc)[4][2], const T (*X)[M2L_NT + 1],
+__device__ __forceinline__ void m2l_operands(T (&kv)[4], T &bv0, T &bv1, const T (*X)[M2lX<T>::XS], const T *tab,
+                                             const int (&base)[4], int ks, int n, int col) {
+    const int b1 = ks >> 4, b2 = (ks >> 2) & 3, b3 = ks & 3;
+    const int toff = KTAB_MID - 7 * ((b1 * 7 + b2) * 7 + b3);
+    bv0 = X[col][4 * ks + n];
+    bv1 = X[col + 16][4 * ks + n];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) kv[rb] = tab[base[rb] + toff];
+}
+
+template <typename T>
+__device__ __forceinline__ void m2l_apply(typename Mma<T>::acc_t (&acc)[4][2], const T (*X)[M2lX<T>::XS],
                                           const T *tab, const int (&base)[4], int wc, int lane) {
     const int n = lane >> 4, col = 32 * wc + (lane & 15);
 #pragma unroll
-    for (int b1 = 0; b1 < 4; ++b1)
+    for (int ks = 0; ks < 64; ++ks) {
+        T kv[4], bv0, bv1;
+        m2l_operands<T>(kv, bv0, bv1, X, tab, base, ks, n, col);
 #pragma unroll
-        for (int b2 = 0; b2 < 4; ++b2)
-#pragma unroll
-            for (int b3 = 0; b3 < 4; ++b3) {
-                const int ks = (b1 * 4 + b2) * 4 + b3;
-                const int toff = KTAB_MID - 7 * ((b1 * 7 + b2) * 7 + b3);
-                const T bv0 = X[4 * ks + n][col], bv1 = X[4 * ks + n][col + 16];
-#pragma unroll
-                for (int rb = 0; rb < 4; ++rb) {
-                    const T kv = tab[base[rb] + toff];
-                    acc[rb][0] = Mma<T>::op(kv, bv0, acc[rb][0]);
-                    acc[rb][1] = Mma<T>::op(kv, bv1, acc[rb][1]);
-                }
-            }
+        for (int rb = 0; rb < 4; ++rb) {
+            acc[rb][0] = Mma<T>::op(kv[rb], bv0, acc[rb][0]);
+            acc[rb][1] = Mma<T>::op(kv[rb], bv1, acc[rb][1]);
+        }
+    }
 }
 
 // Staging of X: each thread owns row xr and the columns j = xj, xj + 2, ...
@@ -573,9 +601,9 @@ __device__ __forceinline__ void m2l_fetch(T (&pre)[M2L_PRE], const int64_t *cbas
     }
 }
 template <typename T>
-__device__ __forceinline__ void m2l_store(T (*X)[M2L_NT + 1], const T (&pre)[M2L_PRE], int xr, int xj) {
+__device__ __forceinline__ void m2l_store(T (*X)[M2lX<T>::XS], const T (&pre)[M2L_PRE], int xr, int xj) {
 #pragma unroll
-    for (int i = 0; i < M2L_PRE; ++i) X[xr][xj + 2 * i] = pre[i];
+    for (int i = 0; i < M2L_PRE; ++i) X[xj + 2 * i][xr] = pre[i];
 }
 
 // offset-major M2L for one right-hand side: one block per (offset, kind, column
@@ -592,8 +620,10 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
     const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = wave & 3, wc = wave >> 2;
-    __shared__ T X[NN][M2L_NT + 1];
+    __shared__ T X[M2L_NT][M2lX<T>::XS];
     __shared__ T tab[KTAB];
+    __shared__ double rd[343];
+    __shared__ T ird[343];
     __shared__ int64_t cbase[M2L_NT];
     int base[4];
     m2l_row_base(base, wr, lane);
@@ -612,12 +642,13 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
         return (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + xr;
     };
     T pre[M2L_PRE];
-    __syncthreads();                              // cbase visible
+    m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
+    __syncthreads();                              // cbase, rd and ird visible
     m2l_fetch(pre, cbase, MM, loff(1), xj);
     for (int lag = 1; lag <= nlag; ++lag) {
         __syncthreads();                          // the previous products are done with X and tab
         m2l_store<T>(X, pre, xr, xj);
-        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, ds, cgt, 2.0 * cl);
+        m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
         __syncthreads();
         if (lag < nlag) m2l_fetch(pre, cbase, MM, loff(lag + 1), xj);
         m2l_apply<T>(acc, X, tab, base, wc, lane);
@@ -658,8 +689,10 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = wave & 3, wc = wave >> 2;
     const int parity = (k + 1) & 1;
-    __shared__ T X[NN][M2L_NT + 1];
+    __shared__ T X[M2L_NT][M2lX<T>::XS];
     __shared__ T tab[KTAB];
+    __shared__ double rd[343];
+    __shared__ T ird[343];
     __shared__ int64_t cbase[M2L_NT];
     int base[4];
     m2l_row_base(base, wr, lane);
@@ -695,7 +728,11 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
         const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
         __syncthreads();
         m2l_store<T>(X, pre, xr, xj);
-        m2l_table<T>(tab, ox, oy, oz, lag, kind, gs, ds, cgt, 2.0 * cl);
+        if (lag == 1) {                           // a new source entry: its offset's distances
+            m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
+            __syncthreads();
+        }
+        m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
         __syncthreads();
         if (it + 1 < nitem) m2l_fetch(pre, cbase, MM, loff(it + 1), xj);
         m2l_apply<T>(acc, X, tab, base, wc, lane);
