@@ -586,24 +586,34 @@ __device__ __forceinline__ void m2l_apply(typename Mma<T>::acc_t (&acc)[4][2], c
     }
 }
 
-// Staging of X: each thread owns row xr and the columns j = xj, xj + 2, ...
+// Staging of X: each thread owns the row pair (2 xr, 2 xr + 1) and the columns
+// j = xg, xg + 4, ..., so every global load and LDS store moves two adjacent
+// rows at once (16-byte moment loads; column bases are multiples of 256
+// values and the padded column strides keep the LDS stores aligned).
 // m2l_fetch issues the global loads of one lag (all in flight together) into
 // registers; m2l_store writes them to LDS.  The kernels fetch the next lag
 // before the current lag's products, so the loads overlap the matrix cores.
-static constexpr int M2L_PRE = M2L_NT / 2;
+static constexpr int M2L_PRE = M2L_NT / 4;
+template <typename T> struct M2lPair;
+template <> struct M2lPair<double> { typedef double2 type; };
+template <> struct M2lPair<float> { typedef float2 type; };
 template <typename T>
-__device__ __forceinline__ void m2l_fetch(T (&pre)[M2L_PRE], const int64_t *cbase, const double *MM, int64_t loff,
-                                          int xj) {
+__device__ __forceinline__ void m2l_fetch(typename M2lPair<T>::type (&pre)[M2L_PRE], const int64_t *cbase,
+                                          const double *MM, int64_t loff, int xg) {
 #pragma unroll
     for (int i = 0; i < M2L_PRE; ++i) {
-        const int64_t b = cbase[xj + 2 * i];
-        pre[i] = (T)(b >= 0 ? MM[b + loff] : 0.0);
+        const int64_t b = cbase[xg + 4 * i];
+        double2 v = make_double2(0.0, 0.0);
+        if (b >= 0) v = *reinterpret_cast<const double2 *>(MM + b + loff);
+        pre[i].x = (T)v.x;
+        pre[i].y = (T)v.y;
     }
 }
 template <typename T>
-__device__ __forceinline__ void m2l_store(T (*X)[M2lX<T>::XS], const T (&pre)[M2L_PRE], int xr, int xj) {
+__device__ __forceinline__ void m2l_store(T (*X)[M2lX<T>::XS], const typename M2lPair<T>::type (&pre)[M2L_PRE],
+                                          int xr, int xg) {
 #pragma unroll
-    for (int i = 0; i < M2L_PRE; ++i) X[xj + 2 * i][xr] = pre[i];
+    for (int i = 0; i < M2L_PRE; ++i) *reinterpret_cast<typename M2lPair<T>::type *>(&X[xg + 4 * i][2 * xr]) = pre[i];
 }
 
 // offset-major M2L for one right-hand side: one block per (offset, kind, column
@@ -620,7 +630,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
     const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = wave & 3, wc = wave >> 2;
-    __shared__ T X[M2L_NT][M2lX<T>::XS];
+    __shared__ __attribute__((aligned(16))) T X[M2L_NT][M2lX<T>::XS];
     __shared__ T tab[KTAB];
     __shared__ double rd[343];
     __shared__ T ird[343];
@@ -636,21 +646,21 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
         if (tid < ncol) b = ((int64_t)il_src[col_q[col0 + tid]] * WR * 2 * NCH + col_ch[col0 + tid]) * NN;
         cbase[tid] = b;
     }
-    const int xr = tid & (NN - 1), xj = tid >> 8;
+    const int xr = tid & (NN / 2 - 1), xg = tid >> 7;   // row pair, first column
     const int nlag = min(W, k + 1);               // lags whose source interval exists
     auto loff = [&](int lag) {
-        return (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + xr;
+        return (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + 2 * xr;
     };
-    T pre[M2L_PRE];
+    typename M2lPair<T>::type pre[M2L_PRE];
     m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
     __syncthreads();                              // cbase, rd and ird visible
-    m2l_fetch(pre, cbase, MM, loff(1), xj);
+    m2l_fetch<T>(pre, cbase, MM, loff(1), xg);
     for (int lag = 1; lag <= nlag; ++lag) {
         __syncthreads();                          // the previous products are done with X and tab
-        m2l_store<T>(X, pre, xr, xj);
+        m2l_store<T>(X, pre, xr, xg);
         m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
         __syncthreads();
-        if (lag < nlag) m2l_fetch(pre, cbase, MM, loff(lag + 1), xj);
+        if (lag < nlag) m2l_fetch<T>(pre, cbase, MM, loff(lag + 1), xg);
         m2l_apply<T>(acc, X, tab, base, wc, lane);
     }
     for (int rb = 0; rb < 4; ++rb)
@@ -689,7 +699,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wr = wave & 3, wc = wave >> 2;
     const int parity = (k + 1) & 1;
-    __shared__ T X[M2L_NT][M2lX<T>::XS];
+    __shared__ __attribute__((aligned(16))) T X[M2L_NT][M2lX<T>::XS];
     __shared__ T tab[KTAB];
     __shared__ double rd[343];
     __shared__ T ird[343];
@@ -699,7 +709,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
     const double gs = hn * (2.0 / (P - 1)), cgt = cl * ht * (2.0 / (P - 1));
     typename Mma<T>::acc_t acc[4][2];
     for (int rb = 0; rb < 4; ++rb) acc[rb][0] = acc[rb][1] = typename Mma<T>::acc_t{0, 0, 0, 0};
-    const int xr = tid & (NN - 1), xj = tid >> 8;
+    const int xr = tid & (NN / 2 - 1), xg = tid >> 7;   // row pair, first column
     // column offsets within one source cell's moments (the source enters per item)
     if (tid < M2L_NT) {
         int64_t b = -1;
@@ -717,24 +727,24 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
     auto loff = [&](int it) {
         const int q = q0 + it / nlag, lag = it % nlag + 1;
         return (int64_t)il_src[q] * strideS +
-               (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * nrhs * NN + xr;
+               (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * nrhs * NN + 2 * xr;
     };
-    T pre[M2L_PRE];
+    typename M2lPair<T>::type pre[M2L_PRE];
     __syncthreads();                              // cbase visible
-    if (nitem > 0) m2l_fetch(pre, cbase, MM, loff(0), xj);
+    if (nitem > 0) m2l_fetch<T>(pre, cbase, MM, loff(0), xg);
     for (int it = 0; it < nitem; ++it) {
         const int q = q0 + it / nlag, lag = it % nlag + 1;
         const int code = il_code[q];
         const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
         __syncthreads();
-        m2l_store<T>(X, pre, xr, xj);
+        m2l_store<T>(X, pre, xr, xg);
         if (lag == 1) {                           // a new source entry: its offset's distances
             m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
             __syncthreads();
         }
         m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
         __syncthreads();
-        if (it + 1 < nitem) m2l_fetch(pre, cbase, MM, loff(it + 1), xj);
+        if (it + 1 < nitem) m2l_fetch<T>(pre, cbase, MM, loff(it + 1), xg);
         m2l_apply<T>(acc, X, tab, base, wc, lane);
     }
     for (int rb = 0; rb < 4; ++rb)
