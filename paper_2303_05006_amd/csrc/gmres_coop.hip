@@ -1,8 +1,8 @@
 // Device-resident restarted GMRES for Z0 x = b, Section 2.5.
 //
 // One cooperative launch runs whole solves: right Jacobi preconditioning,
-// Arnoldi with classical Gram-Schmidt applied twice, Givens rotations and the
-// restart logic.  blockIdx.y selects an independent system (one right-hand
+// Arnoldi with classical Gram-Schmidt and the DGKS second pass, Givens
+// rotations and the restart logic.  blockIdx.y selects an independent system (one right-hand
 // side, its vectors contiguous); the gridDim.x blocks of a system split its
 // rows.  Grid-wide barriers among a system's blocks separate the phases that
 // read other blocks' rows (SpMV) or other blocks' partial sums (dot products).
@@ -237,11 +237,11 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
     if (blockIdx.x == 0 && threadIdx.x == 0) A.out[2] = 0;
     const int r0 = (int)((int64_t)ne * blockIdx.x / nb), r1 = (int)((int64_t)ne * (blockIdx.x + 1) / nb);
     const size_t vs = (size_t)ne;
-    const bool regs = r1 - r0 <= 32 * GM_RU;   // block-uniform
+    const bool on_chip = r1 - r0 <= 32 * GM_RU;   // block-uniform: rows held in LDS
     const int nu = (r1 - r0 + 31) / 32;
     __shared__ int rc[GM_RU * GM_THREADS];
     __shared__ double ra[GM_RU * GM_THREADS];
-    const unsigned tail = regs ? load_lds_rows(rc, ra, A.ptr, A.col, A.vald, r0, r1) : 0u;
+    const unsigned tail = on_chip ? load_lds_rows(rc, ra, A.ptr, A.col, A.vald, r0, r1) : 0u;
     int rnd = 0;
     // ||b||
     block_dots(A, rnd, 1, A.b, vs, A.b, r0, r1, red);
@@ -278,10 +278,10 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
             double *w = (k & 1) ? A.w1 : A.w0;
             // w = A Dinv V_k, with V_k = wprev * hscale for k >= 1 (rows of other blocks)
             if (k == 0) {
-                if (regs) block_spmv_lds(rc, ra, tail, nu, A.ptr, A.col, A.vald, A.V, 1.0, w, r0, r1);
+                if (on_chip) block_spmv_lds(rc, ra, tail, nu, A.ptr, A.col, A.vald, A.V, 1.0, w, r0, r1);
                 else block_spmv(A.ptr, A.col, A.vald, A.V, 1.0, nullptr, w, r0, r1);
             } else {
-                if (regs) block_spmv_lds(rc, ra, tail, nu, A.ptr, A.col, A.vald, wprev, hscale, w, r0, r1);
+                if (on_chip) block_spmv_lds(rc, ra, tail, nu, A.ptr, A.col, A.vald, wprev, hscale, w, r0, r1);
                 else block_spmv(A.ptr, A.col, A.vald, wprev, hscale, nullptr, w, r0, r1);
                 for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) A.V[(size_t)k * vs + i] = wprev[i] * hscale;
             }
