@@ -104,7 +104,7 @@ def cpu_baseline(workload, rows=8):
         L.orc_history(len(r_), P(r_), P(c_), P(g0), P(ln), P(off), P(vals), m.ne, P(hist), nb, nb, 2, P(out))
         reps += 1
         el = time.perf_counter() - t0
-        if el > 5.0 and reps >= 3:
+        if el > 10.0 and reps >= 3:
             break
     per_sample = el / reps
     per_step = per_sample * m.ne / rows
