@@ -555,10 +555,11 @@ __device__ __forceinline__ void m2l_row_base(int (&base)[4], int wr, int lane) {
     }
 }
 
-// acc (this wave's 64 rows x 32 columns) += K X for the table in LDS.  The
-// operands of k-step ks + 1 are read from LDS before the 8 products of k-step
-// ks are issued (scheduling barriers keep the two apart), so each read has a
-// whole k-step of matrix-core work to complete in.
+// acc (this wave's 64 rows x 32 columns) += K X for the table in LDS.  Per
+// k-step a lane reads its 4 A operands from the table and its 2 B operands
+// from X, all at immediate offsets, and issues 8 products.  The second wave on
+// each SIMD covers the LDS latency (reading a whole k-step ahead measured no
+// faster).
 template <typename T>
 __device__ __forceinline__ void m2l_operands(T (&kv)[4], T &bv0, T &bv1, const T (*X)[M2lX<T>::XS], const T *tab,
                                              const int (&base)[4], int ks, int n, int col) {
