@@ -46,6 +46,7 @@ struct FarLevel {
     int *leaf_cells = nullptr, *parent_cells = nullptr;
     int *child_beg = nullptr, *child_end = nullptr;                // children at level+1
     double *MM = nullptr;     // [n][WR][2][NCH][nrhs][NN]
+    float *MM32 = nullptr;    // FP32 copy of MM staged by the reduced forms' M2L (one right-hand side)
     double *LC = nullptr;     // [n][NCH][nrhs][NN]
     double *PEND = nullptr;   // [n][2][NCH][nrhs][NN]
     double *tw = nullptr;     // [M][2][P]: l_m and dl_m/dt at target step q = 1..M
@@ -223,6 +224,7 @@ void ifmm_setup(tdbem_ctx *C) {
         FL.child_beg = fup(C, L.child_beg);
         FL.child_end = fup(C, L.child_end);
         FL.MM = falloc<double>(C, (size_t)L.n * F->WR * 2 * NCH * nr * NN);
+        if (nr == 1 && C->cfg.precision != TDBEM_FP64) FL.MM32 = falloc<float>(C, (size_t)L.n * F->WR * 2 * NCH * NN);
         FL.LC = falloc<double>(C, (size_t)L.n * NCH * nr * NN);
         FL.PEND = falloc<double>(C, (size_t)L.n * 2 * NCH * nr * NN);
         // time tables: targets t = (k+1) d_t + q dt, q = 1..M, in the target interval
@@ -625,7 +627,7 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
                                                          const int *tile_col0, const int *tile_ncol, const int *col_q,
                                                          const int *col_ch, const int *il_src, const double *MM, int WR,
                                                          int k, int W, double hn, double ds, double ht, double cl,
-                                                         double *YB) {
+                                                         double *YB, const float *MMf) {
     const int tile = blockIdx.x;
     const int code = tile_code[tile], kind = tile_kind[tile], col0 = tile_col0[tile], ncol = tile_ncol[tile];
     const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
@@ -652,17 +654,46 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
     auto loff = [&](int lag) {
         return (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + 2 * xr;
     };
-    typename M2lPair<T>::type pre[M2L_PRE];
     m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
-    __syncthreads();                              // cbase, rd and ird visible
-    m2l_fetch<T>(pre, cbase, MM, loff(1), xg);
-    for (int lag = 1; lag <= nlag; ++lag) {
-        __syncthreads();                          // the previous products are done with X and tab
-        m2l_store<T>(X, pre, xr, xg);
-        m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
-        __syncthreads();
-        if (lag < nlag) m2l_fetch<T>(pre, cbase, MM, loff(lag + 1), xg);
-        m2l_apply<T>(acc, X, tab, base, wc, lane);
+    if constexpr (sizeof(T) == 4) {
+        // FP32 form: X from the FP32 copy of the moments (the same values the
+        // conversion at staging gave), four rows per 16-byte load and store;
+        // thread = row quad xq and columns xh, xh + 8, ...
+        const int xq = tid & 63, xh = tid >> 6;
+        auto loff4 = [&](int lag) {
+            return (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * NN + 4 * xq;
+        };
+        float4 p4[M2L_NT / 8];
+        auto fetch4 = [&](int64_t lo) {
+#pragma unroll
+            for (int i = 0; i < M2L_NT / 8; ++i) {
+                const int64_t b = cbase[xh + 8 * i];
+                p4[i] = b >= 0 ? *reinterpret_cast<const float4 *>(MMf + b + lo) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        };
+        __syncthreads();                          // cbase, rd and ird visible
+        fetch4(loff4(1));
+        for (int lag = 1; lag <= nlag; ++lag) {
+            __syncthreads();                      // the previous products are done with X and tab
+#pragma unroll
+            for (int i = 0; i < M2L_NT / 8; ++i) *reinterpret_cast<float4 *>(&X[xh + 8 * i][4 * xq]) = p4[i];
+            m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
+            __syncthreads();
+            if (lag < nlag) fetch4(loff4(lag + 1));
+            m2l_apply<T>(acc, X, tab, base, wc, lane);
+        }
+    } else {
+        typename M2lPair<T>::type pre[M2L_PRE];
+        __syncthreads();                          // cbase, rd and ird visible
+        m2l_fetch<T>(pre, cbase, MM, loff(1), xg);
+        for (int lag = 1; lag <= nlag; ++lag) {
+            __syncthreads();                      // the previous products are done with X and tab
+            m2l_store<T>(X, pre, xr, xg);
+            m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
+            __syncthreads();
+            if (lag < nlag) m2l_fetch<T>(pre, cbase, MM, loff(lag + 1), xg);
+            m2l_apply<T>(acc, X, tab, base, wc, lane);
+        }
     }
     for (int rb = 0; rb < 4; ++rb)
         for (int cb = 0; cb < 2; ++cb) {
@@ -762,6 +793,13 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
         }
 }
 
+// FP32 copy of a level's moments for the reduced forms' M2L (rounded once here
+// instead of at every staging of X)
+__global__ void k_mm_to_f32(int64_t n, const double *__restrict__ src, float *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (float)src[i];
+}
+
 // launch of the M2L of one level at gate k
 template <typename T>
 static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
@@ -769,10 +807,16 @@ static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
     const int nr = C->nrhs;
     if (nr == 1) {
         if (FL.ntile > 0) {
+            if (sizeof(T) == 4) {
+                PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
+                const int64_t nmm = (int64_t)FL.n * F->WR * 2 * NCH * NN;
+                hipLaunchKernelGGL(k_mm_to_f32, dim3((unsigned)((nmm + 255) / 256)), dim3(256), 0, s, nmm, FL.MM,
+                                   FL.MM32);
+            }
             PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
             hipLaunchKernelGGL(k_m2l_off<T>, dim3(FL.ntile), dim3(M2L_THREADS), 0, s, FL.tile_code, FL.tile_kind,
                                FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, F->WR, k, F->W, FL.hn,
-                               FL.ds, FL.ht, C->c, FL.YB);
+                               FL.ds, FL.ht, C->c, FL.YB, (const float *)FL.MM32);
         }
         PhaseScope ps(C->prof, TDBEM_PH_M2L_SUM, s);
         hipLaunchKernelGGL(k_m2l_reduce, dim3(FL.n, NCH), dim3(NN), 0, s, FL.n, FL.il_off, FL.YB, FL.PEND, (k + 1) & 1,
