@@ -113,6 +113,21 @@ def test_m2l_row_pair_staging_covers_the_tile_once():
     assert (hit == 1).all()
 
 
+def test_m2l_row_quad_staging_of_the_fp32_form_covers_the_tile_once():
+    """FP32 form: thread (row quad xq, first column xh) stages rows 4 xq..4 xq + 3
+    of columns xh + 8 i with one 16-byte load and store each; the column stride
+    of 260 floats keeps the stores 16-byte aligned."""
+    XS = NN + 4
+    hit = np.zeros((NN, M2L_NT), int)
+    for tid in range(512):
+        xq, xh = tid & 63, tid >> 6
+        for i in range(M2L_NT // 8):
+            col = xh + 8 * i
+            assert ((col * XS + 4 * xq) * 4) % 16 == 0
+            hit[4 * xq:4 * xq + 4, col] += 1
+    assert (hit == 1).all()
+
+
 def test_m2l_table_reads_are_in_range_and_index_the_lattice_difference():
     """A operand of row (a, m) at k-step (b, n): base + KTAB_MID - 7 (49 b1 +
     7 b2 + b3) must be the table entry of a - b per axis and m - n."""
