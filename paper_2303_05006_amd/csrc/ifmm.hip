@@ -46,7 +46,7 @@ struct FarLevel {
     int *leaf_cells = nullptr, *parent_cells = nullptr;
     int *child_beg = nullptr, *child_end = nullptr;                // children at level+1
     double *MM = nullptr;     // [n][WR][2][NCH][nrhs][NN]
-    float *MM32 = nullptr;    // FP32 copy of MM staged by the reduced forms' M2L (one right-hand side)
+    float *MM32 = nullptr;    // FP32 copy of MM staged by the reduced forms' M2L
     double *LC = nullptr;     // [n][NCH][nrhs][NN]
     double *PEND = nullptr;   // [n][2][NCH][nrhs][NN]
     double *tw = nullptr;     // [M][2][P]: l_m and dl_m/dt at target step q = 1..M
@@ -224,7 +224,7 @@ void ifmm_setup(tdbem_ctx *C) {
         FL.child_beg = fup(C, L.child_beg);
         FL.child_end = fup(C, L.child_end);
         FL.MM = falloc<double>(C, (size_t)L.n * F->WR * 2 * NCH * nr * NN);
-        if (nr == 1 && C->cfg.precision != TDBEM_FP64) FL.MM32 = falloc<float>(C, (size_t)L.n * F->WR * 2 * NCH * NN);
+        if (C->cfg.precision != TDBEM_FP64) FL.MM32 = falloc<float>(C, (size_t)L.n * F->WR * 2 * NCH * nr * NN);
         FL.LC = falloc<double>(C, (size_t)L.n * NCH * nr * NN);
         FL.PEND = falloc<double>(C, (size_t)L.n * 2 * NCH * nr * NN);
         // time tables: targets t = (k+1) d_t + q dt, q = 1..M, in the target interval
@@ -721,7 +721,7 @@ template <typename T>
 __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt(const int *il_off, const int *il_src, const int *il_code,
                                                          const double *MM, int WR, int k, int W, double hn, double ds,
                                                          double ht, double cl, const double *PEND, double *LC,
-                                                         int nrhs) {
+                                                         int nrhs, const float *MMf) {
     const int O = blockIdx.x, kind = blockIdx.y;
     const int c0 = kind == 0 ? 0 : 3, nc = kind == 0 ? 3 : 4;
     const int ncolt = nc * nrhs;
@@ -761,23 +761,60 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_tgt
         return (int64_t)il_src[q] * strideS +
                (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * nrhs * NN + 2 * xr;
     };
-    typename M2lPair<T>::type pre[M2L_PRE];
-    __syncthreads();                              // cbase visible
-    if (nitem > 0) m2l_fetch<T>(pre, cbase, MM, loff(0), xg);
-    for (int it = 0; it < nitem; ++it) {
-        const int q = q0 + it / nlag, lag = it % nlag + 1;
-        const int code = il_code[q];
-        const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
-        __syncthreads();
-        m2l_store<T>(X, pre, xr, xg);
-        if (lag == 1) {                           // a new source entry: its offset's distances
-            m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
+    if constexpr (sizeof(T) == 4) {
+        // FP32 form: X from the FP32 copy of the moments, four rows per
+        // 16-byte load and store (thread = row quad xq, columns xh + 8 i)
+        const int xq = tid & 63, xh = tid >> 6;
+        auto loff4 = [&](int it) {
+            const int q = q0 + it / nlag, lag = it % nlag + 1;
+            return (int64_t)il_src[q] * strideS +
+                   (int64_t)(((k + 1 - lag) % WR) * 2 + (lag == W ? 1 : 0)) * NCH * nrhs * NN + 4 * xq;
+        };
+        float4 p4[M2L_NT / 8];
+        auto fetch4 = [&](int64_t lo) {
+#pragma unroll
+            for (int i = 0; i < M2L_NT / 8; ++i) {
+                const int64_t b = cbase[xh + 8 * i];
+                p4[i] = b >= 0 ? *reinterpret_cast<const float4 *>(MMf + b + lo) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        };
+        __syncthreads();                          // cbase visible
+        if (nitem > 0) fetch4(loff4(0));
+        for (int it = 0; it < nitem; ++it) {
+            const int q = q0 + it / nlag, lag = it % nlag + 1;
+            const int code = il_code[q];
+            const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
             __syncthreads();
+#pragma unroll
+            for (int i = 0; i < M2L_NT / 8; ++i) *reinterpret_cast<float4 *>(&X[xh + 8 * i][4 * xq]) = p4[i];
+            if (lag == 1) {                       // a new source entry: its offset's distances
+                m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
+                __syncthreads();
+            }
+            m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
+            __syncthreads();
+            if (it + 1 < nitem) fetch4(loff4(it + 1));
+            m2l_apply<T>(acc, X, tab, base, wc, lane);
         }
-        m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
-        __syncthreads();
-        if (it + 1 < nitem) m2l_fetch<T>(pre, cbase, MM, loff(it + 1), xg);
-        m2l_apply<T>(acc, X, tab, base, wc, lane);
+    } else {
+        typename M2lPair<T>::type pre[M2L_PRE];
+        __syncthreads();                          // cbase visible
+        if (nitem > 0) m2l_fetch<T>(pre, cbase, MM, loff(0), xg);
+        for (int it = 0; it < nitem; ++it) {
+            const int q = q0 + it / nlag, lag = it % nlag + 1;
+            const int code = il_code[q];
+            const int ox = code / 49 - 3, oy = (code / 7) % 7 - 3, oz = code % 7 - 3;
+            __syncthreads();
+            m2l_store<T>(X, pre, xr, xg);
+            if (lag == 1) {                       // a new source entry: its offset's distances
+                m2l_dist<T>(rd, ird, ox, oy, oz, gs, ds);
+                __syncthreads();
+            }
+            m2l_table<T>(tab, rd, ird, lag, kind, cgt, 2.0 * cl);
+            __syncthreads();
+            if (it + 1 < nitem) m2l_fetch<T>(pre, cbase, MM, loff(it + 1), xg);
+            m2l_apply<T>(acc, X, tab, base, wc, lane);
+        }
     }
     for (int rb = 0; rb < 4; ++rb)
         for (int cb = 0; cb < 2; ++cb) {
@@ -805,14 +842,14 @@ template <typename T>
 static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
     FarState *F = C->far;
     const int nr = C->nrhs;
+    if (sizeof(T) == 4 && (nr > 1 || FL.ntile > 0)) {
+        // the reduced forms stage X from an FP32 copy of this level's moments
+        PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
+        const int64_t nmm = (int64_t)FL.n * F->WR * 2 * NCH * nr * NN;
+        hipLaunchKernelGGL(k_mm_to_f32, dim3((unsigned)((nmm + 255) / 256)), dim3(256), 0, s, nmm, FL.MM, FL.MM32);
+    }
     if (nr == 1) {
         if (FL.ntile > 0) {
-            if (sizeof(T) == 4) {
-                PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
-                const int64_t nmm = (int64_t)FL.n * F->WR * 2 * NCH * NN;
-                hipLaunchKernelGGL(k_mm_to_f32, dim3((unsigned)((nmm + 255) / 256)), dim3(256), 0, s, nmm, FL.MM,
-                                   FL.MM32);
-            }
             PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
             hipLaunchKernelGGL(k_m2l_off<T>, dim3(FL.ntile), dim3(M2L_THREADS), 0, s, FL.tile_code, FL.tile_kind,
                                FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, F->WR, k, F->W, FL.hn,
@@ -825,7 +862,7 @@ static void m2l_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
         PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
         hipLaunchKernelGGL(k_m2l_tgt<T>, dim3(FL.n, 2, (4 * nr + M2L_NT - 1) / M2L_NT), dim3(M2L_THREADS), 0, s,
                            FL.il_off, FL.il_src, FL.il_code, FL.MM, F->WR, k, F->W, FL.hn, FL.ds, FL.ht, C->c, FL.PEND, FL.LC,
-                           nr);
+                           nr, (const float *)FL.MM32);
     }
 }
 
