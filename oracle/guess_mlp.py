@@ -87,3 +87,46 @@ def adam(p, gr, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1.0 - b1 ** t)
     vh = v / (1.0 - b2 ** t)
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ------------------------------------------------------------ inference precision
+def bf16(a):
+    """Round to the nearest bfloat16 value, ties to even (the 16 low bits of the
+    float32 value rounded away), returned as FP64.  Inputs are first rounded
+    to float32, as the inference kernel holds them."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def g_bf16(p, x):
+    """g(x) with the roundings the inference definition states: the features x
+    (already bf16 values), W1, W2 and the first hidden layer rounded to bf16;
+    everything else, and every sum, in FP64."""
+    W1, b1, W2, b2, w3, b3 = unpack(p)
+    W1b, W2b = bf16(W1), bf16(W2)
+    x = np.asarray(x, dtype=np.float64)
+
+    def o(xx):
+        h1 = bf16(relu(xx @ W1b + b1))
+        return relu(h1 @ W2b + b2) @ w3 + b3
+    return 0.5 * (o(x) - o(-x))
+
+
+def g_bf16_bound(p, x):
+    """First-order bound on |g_bf16(x) - g(x)| per sample, from the three bf16
+    roundings (relative error at most u = 2^-9 each; relu is 1-Lipschitz):
+      |d a1_k| <= u sum_f |x_f W1_fk|,   |d h1_k| <= |d a1_k| + u |h1_k|,
+      |d a2_c| <= sum_k |d h1_k| |W2_kc| + u sum_k |h1_k W2_kc|,
+      |d o|    <= sum_c |w3_c| |d a2_c|,  and |d g| <= (|d o(x)| + |d o(-x)|) / 2."""
+    u = 2.0 ** -9
+    W1, b1, W2, b2, w3, b3 = unpack(p)
+    x = np.asarray(x, dtype=np.float64)
+
+    def do(xx):
+        h1 = relu(xx @ W1 + b1)
+        da1 = u * (np.abs(xx) @ np.abs(W1))
+        dh1 = da1 + u * np.abs(h1)
+        da2 = dh1 @ np.abs(W2) + u * (np.abs(h1) @ np.abs(W2))
+        return da2 @ np.abs(w3)
+    return 0.5 * (do(x) + do(-x))

@@ -25,6 +25,13 @@ from its earlier work; it reproduces quadratics, which the window truncation of
 the fast code needs, and is C^1 inside the interval).
 Channels: 0-2 vector potential (kernel dU/dt = c d U^{d-1}, d = 2), 3 scalar
 potential (U^d), 4-6 magnetic vector potential (U^d, grad_y on the source).
+
+Variants of Section 4.3: the CFIE (CFIE1 of Eq. cfie, CFIE2 = dt EFIE + dt MFIE,
+CFIE3 = dt EFIE + MFIE) weights the magnetic channels' target derivative
+(kd l_m' + zeta l_m); the second time derivative of the vector potential is
+split between kernel and interpolant (dU/dt with l_m', Eq. ddotA_fmm), or put
+on the kernel (d^2U/dt^2 = c^2 d (d-1) U^{d-2} with l_m) or on the
+interpolant (U with l_m'').
 """
 from __future__ import annotations
 
@@ -64,6 +71,51 @@ def lagrange(p, xi):
             d = d + t
         der[..., n] = d / den
     return val, der
+
+
+def lagrange_d2(p, xi):
+    """Second derivatives l_n''(xi) of the Lagrange cardinal polynomials:
+    sum over ordered pairs (k, q), k != q, both != n, of prod_{m != n, k, q} (xi - w_m),
+    divided by prod_{m != n} (w_n - w_m)."""
+    w = nodes(p)
+    xi = np.asarray(xi, float)
+    out = np.zeros(xi.shape + (p,))
+    for n in range(p):
+        others = [m for m in range(p) if m != n]
+        den = np.prod([w[n] - w[m] for m in others])
+        acc = np.zeros(xi.shape)
+        for k in others:
+            for q in others:
+                if q == k:
+                    continue
+                t = np.ones(xi.shape)
+                for m in others:
+                    if m != k and m != q:
+                        t = t * (xi - w[m])
+                acc = acc + t
+        out[..., n] = acc / den
+    return out
+
+
+def chi_fd_d2(p, xi):
+    """Second derivatives of the CHI-FD cardinal functions (piecewise linear)."""
+    w = nodes(p)
+    h = w[1] - w[0]
+    xi = np.asarray(xi, float)
+    seg = np.clip(np.floor((xi + 1.0) / h).astype(int), 0, p - 2)
+    t = (xi - w[seg]) / h
+    ddH = [12 * t - 6, 6 * t - 4, -12 * t + 6, 6 * t - 2]
+    out = np.zeros(xi.shape + (p,))
+    for n in range(p):
+        f = np.zeros(p)
+        f[n] = 1.0
+        slope = np.zeros(p)
+        slope[0] = (-3 * f[0] + 4 * f[1] - f[2]) / (2 * h)
+        slope[p - 1] = (3 * f[p - 1] - 4 * f[p - 2] + f[p - 3]) / (2 * h)
+        slope[1:p - 1] = (f[2:] - f[:p - 2]) / (2 * h)
+        fa, fb, sa, sb = f[seg], f[seg + 1], slope[seg], slope[seg + 1]
+        out[..., n] = (ddH[0] * fa + ddH[1] * h * sa + ddH[2] * fb + ddH[3] * h * sb) / (h * h)
+    return out
 
 
 def chi_fd(p, xi):
@@ -109,7 +161,7 @@ class Cell:
 class Hierarchy:
     """Octree over edge midpoints and the time intervals of each level."""
 
-    def __init__(self, mesh, cdt, leaf_max, min_level=2):
+    def __init__(self, mesh, cdt, leaf_max, min_level=2, causal_guard=False):
         lo, hi = mesh.xyz.min(axis=0), mesh.xyz.max(axis=0)
         self.side = float((hi - lo).max())
         self.origin = 0.5 * (lo + hi) - 0.5 * self.side
@@ -155,8 +207,19 @@ class Hierarchy:
             self.ilist.append(il)
         # time hierarchy
         d_s = self.side / 2 ** self.lmax
+        reach = d_s
+        if causal_guard:
+            # the cell side minus twice the largest distance from an edge midpoint
+            # to a point of its basis support (a vertex of its two triangles), so
+            # that no far pair can interact within one interval (the paper's
+            # Remark 1 takes the cell side alone)
+            delta = 0.5 * float(mesh.elen.max())
+            for side in (0, 1):
+                o = mesh.xyz[mesh.efree[:, side]]
+                delta = max(delta, float(np.linalg.norm(o - mid, axis=1).max()))
+            reach = d_s - 2.0 * delta
         self.Mt = [0] * (self.lmax + 1)
-        self.Mt[self.lmax] = int(math.floor(d_s / cdt))
+        self.Mt[self.lmax] = int(math.floor(reach / cdt))
         for l in range(self.lmax - 1, 1, -1):
             self.Mt[l] = 2 * self.Mt[l + 1]
 
@@ -195,6 +258,13 @@ class Hierarchy:
 
 
 # ----------------------------------------------------------------- kernels
+def kernel_U2(c):
+    """d^2 U^d / dt^2 = c^2 d (d - 1) U^{d-2} = 2 c^2 [c(t-s) > r] / r (d = 2)."""
+    def k2(r, tau):
+        return np.where(c * tau - r > 0.0, 2.0 * c * c / r, 0.0)
+    return k2
+
+
 def kernel_U(c):
     """U^d (d = 2) and dU^d/dt = 2 c (c(t-s) - r)_+ / r (Eq. U)."""
     def k0(r, tau):
@@ -210,7 +280,7 @@ class IFMM:
     """Far field of the fast TDBEM for a given current history (all-interval M2L)."""
 
     def __init__(self, mesh, dt, theta, zeta, eps, mu, p_s=4, p_t=4, leaf_max=64, kernels=None,
-                 interp_t="lagrange", widen=False):
+                 interp_t="lagrange", widen=False, causal_guard=False, cfie=1, dt2="split"):
         self.m = mesh
         # interpolation boxes: the cells, optionally widened by the largest per-axis
         # distance from an edge midpoint to a vertex of the edge's two triangles
@@ -221,15 +291,25 @@ class IFMM:
                 self.delta = max(self.delta, float(np.abs(mesh.xyz[v] - mid).max()))
         assert interp_t in ("lagrange", "chi")
         self._tcard = (lambda xi: lagrange(self.pt, xi)) if interp_t == "lagrange" else (lambda xi: chi_fd(self.pt, xi))
+        self._tcard2 = (lambda xi: lagrange_d2(self.pt, xi)) if interp_t == "lagrange" else (lambda xi: chi_fd_d2(self.pt, xi))
+        assert dt2 in ("split", "kernel", "interp")
+        self.dt2 = dt2
+        # weights of the MFIE's time derivative and of the MFIE (Section 4.3.1)
+        self.kd, self.kz = {1: (1.0, zeta), 2: (1.0, 0.0), 3: (0.0, zeta)}[cfie]
         self.c = 1.0 / math.sqrt(eps * mu)
         self.eta = math.sqrt(mu / eps)
         self.dt, self.cdt = dt, self.c * dt
         self.theta, self.zeta, self.eps, self.mu = theta, zeta, eps, mu
         self.ps, self.pt = p_s, p_t
-        self.H = Hierarchy(mesh, self.cdt, leaf_max)
+        self.H = Hierarchy(mesh, self.cdt, leaf_max, causal_guard=causal_guard)
         if self.H.Mt[self.H.lmax] < 1:
             raise ValueError("time hierarchy breaks down (M_t = 0, Remark 1)")
-        self.k1, self.k0 = kernels if kernels is not None else kernel_U(self.c)
+        if kernels is None:
+            self.k1, self.k0 = kernel_U(self.c)
+            self.k2 = kernel_U2(self.c)
+        else:
+            self.k1, self.k0 = kernels[0], kernels[1]
+            self.k2 = kernels[2] if len(kernels) > 2 else None
         self._tables()
 
     # per-edge P2M and L2P weights at the 3-point rule of both triangles
@@ -347,7 +427,7 @@ class IFMM:
                     n_k = min(KT - lag, KS)
                     if n_k <= 0:
                         continue
-                    K1, K0 = self._m2l_cached(l, off, lag)
+                    K1, K0 = self._m2l_offset(l, np.array(off), lag)
                     x = src[:, :n_k]
                     LC[O_idx, lag:lag + n_k, 0:3] += x[:, :, 0:3] @ K1.T
                     LC[O_idx, lag:lag + n_k, 3:7] += x[:, :, 3:7] @ K0.T
@@ -362,8 +442,11 @@ class IFMM:
                             xi = (a * self.dt - (kt + 0.5) * 2 * ht) / ht
                             v, d = self._tcard(np.array([xi]))
                             v, d = v[0], d[0] / ht
+                            dd = self._tcard2(np.array([xi]))[0] / (ht * ht)
+                            wa = {"split": d, "kernel": v, "interp": dd}[self.dt2]
+                            wp = self.kd * d + self.kz * v
                             L = lc[kt].reshape(7, n3, self.pt)
-                            tw = np.stack([d, d, d, v, d + self.zeta * v, d + self.zeta * v, d + self.zeta * v])  # [7, m]
+                            tw = np.stack([wa, wa, wa, v, wp, wp, wp])  # [7, m]
                             Lt = np.einsum('cbm,cm->cb', L, tw)
                             far[a - 1, O.edges] += np.einsum('jcb,cb->j', self.El[O.edges], Lt)
                 else:
@@ -373,14 +456,6 @@ class IFMM:
                             A = self._m2m_matrix(l, ch, oi, h)          # [(a',m'), (a,m)]
                             acc[h:2 * KT + h:2] += lc @ A.T
         return far
-
-    def _m2l_cached(self, l, off, lag):
-        if not hasattr(self, "_cache"):
-            self._cache = {}
-        key = (l, off, lag)
-        if key not in self._cache:
-            self._cache[key] = self._m2l_offset(l, np.array(off), lag)
-        return self._cache[key]
 
     def _m2l_offset(self, l, off, lag):
         """M2L operators (dU/dt and U node values) for a source cell at integer
@@ -398,6 +473,7 @@ class IFMM:
         R = r[:, None, :, None]
         T = tau[None, :, None, :]
         n_sp = ps ** 3
-        K1 = self.k1(R, T).reshape(n_sp * pt, n_sp * pt)
         K0 = self.k0(R, T).reshape(n_sp * pt, n_sp * pt)
-        return K1, K0
+        ka = {"split": self.k1, "kernel": self.k2, "interp": self.k0}[self.dt2]
+        KA = ka(R, T).reshape(n_sp * pt, n_sp * pt)     # vector-potential channels
+        return KA, K0

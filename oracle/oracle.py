@@ -52,11 +52,11 @@ def lib():
         P = ctypes.c_void_p
         _LIB.orc_bspline.restype = d
         _LIB.orc_bspline.argtypes = [i, d]
-        _LIB.orc_tri_integrals.argtypes = [P, P, i, d, d, d, i, i, P]
-        _LIB.orc_zpairs.argtypes = [P, P, P, P, P, d, d, d, d, d, l, P, P, i, P, i]
-        _LIB.orc_zrows.argtypes = [P, P, i, P, P, P, i, P, d, d, d, d, d, i, P, i, P, i, i]
+        _LIB.orc_tri_integrals.argtypes = [P, P, i, d, d, d, d, i, i, P]
+        _LIB.orc_zpairs.argtypes = [P, P, P, P, P, d, d, d, d, d, d, l, P, P, i, P, i]
+        _LIB.orc_zrows.argtypes = [P, P, i, P, P, P, i, P, d, d, d, d, d, d, i, P, i, P, i, i]
         _LIB.orc_gram.argtypes = [P, P, P, P, P, l, P, P, P]
-        _LIB.orc_vinc.argtypes = [P, P, P, P, P, i, P, d, d, d, d, d, P]
+        _LIB.orc_vinc.argtypes = [P, P, P, P, P, i, P, d, d, d, d, d, d, P]
         _LIB.orc_history.argtypes = [l, P, P, P, P, P, P, i, P, i, i, i, P]
     return _LIB
 
@@ -124,8 +124,21 @@ class Mesh:
 # coefficients
 # --------------------------------------------------------------------------
 
+def cfie_weights(cfie, zeta):
+    """Weights (kd, zeta) of the MFIE's time derivative and of the MFIE in the
+    three CFIEs of Section 4.3.1: CFIE1 = dt EFIE + dt MFIE + MFIE (Eq. cfie),
+    CFIE2 = dt EFIE + dt MFIE, CFIE3 = dt EFIE + MFIE."""
+    if cfie == 1:
+        return 1.0, zeta
+    if cfie == 2:
+        return 1.0, 0.0
+    if cfie == 3:
+        return 0.0, zeta
+    raise ValueError(f"unknown CFIE variant {cfie}")
+
+
 def material(eps=None, mu=None):
-    from paper_2303_05006_amd.inputs import EPS0, MU0
+    from oracle.constants import EPS0, MU0
     return (EPS0 if eps is None else eps), (MU0 if mu is None else mu)
 
 
@@ -134,42 +147,44 @@ def max_lag(mesh: Mesh, cdt: float) -> int:
     return int(math.floor(ext / cdt)) + 4
 
 
-def zpairs(mesh: Mesh, pi, pj, cdt, theta, zeta, eps=None, mu=None, G=None, nthreads=0):
+def zpairs(mesh: Mesh, pi, pj, cdt, theta, zeta, eps=None, mu=None, G=None, nthreads=0, cfie=1):
     """Dense lag strips Zt^(g)_{ij}, g = 0..G-1 (g = 0 unused), for pairs (pi, pj)."""
     eps, mu = material(eps, mu)
+    kd, zeta = cfie_weights(cfie, zeta)
     pi = np.ascontiguousarray(pi, dtype=np.int32)
     pj = np.ascontiguousarray(pj, dtype=np.int32)
     if G is None:
         G = max_lag(mesh, cdt) + 1
     out = np.zeros((len(pi), G), dtype=np.float64)
     lib().orc_zpairs(_p(mesh.xyz), _p(mesh.tri), _p(mesh.etri), _p(mesh.efree), _p(mesh.elen),
-                     cdt, eps, mu, theta, zeta, len(pi), _p(pi), _p(pj), G, _p(out), nthreads)
+                     cdt, eps, mu, theta, zeta, kd, len(pi), _p(pi), _p(pj), G, _p(out), nthreads)
     return out
 
 
-def zrows(mesh: Mesh, rows, cdt, theta, zeta, eps=None, mu=None, G=None, nthreads=0, terms=15):
+def zrows(mesh: Mesh, rows, cdt, theta, zeta, eps=None, mu=None, G=None, nthreads=0, terms=15, cfie=1):
     """Dense J-form rows out[r, j, g] = Zt^(g)_{rows[r], j}.  ``terms`` selects
     parts of the operator (1 vector, 2 scalar, 4 magnetic potential, 8 MFIE
     identity term) for the pin tests; 15 is the full operator."""
     eps, mu = material(eps, mu)
+    kd, zeta = cfie_weights(cfie, zeta)
     rows = np.ascontiguousarray(rows, dtype=np.int32)
     if G is None:
         G = max_lag(mesh, cdt) + 1
     out = np.zeros((len(rows), mesh.ne, G))
     lib().orc_zrows(_p(mesh.xyz), _p(mesh.tri), len(mesh.tri), _p(mesh.etri), _p(mesh.efree),
-                    _p(mesh.elen), mesh.ne, _p(mesh.tedge), cdt, eps, mu, theta, zeta,
+                    _p(mesh.elen), mesh.ne, _p(mesh.tedge), cdt, eps, mu, theta, zeta, kd,
                     len(rows), _p(rows), G, _p(out), nthreads, int(terms))
     return out
 
 
-def zdense(mesh: Mesh, cdt, theta, zeta, eps=None, mu=None, nthreads=0, chunk=64):
+def zdense(mesh: Mesh, cdt, theta, zeta, eps=None, mu=None, nthreads=0, chunk=64, cfie=1):
     """All-pairs J-form tensor Z[g, i, j] for the conventional method."""
     ne = mesh.ne
     G = max_lag(mesh, cdt) + 1
     Z = np.zeros((G, ne, ne))
     for r0 in range(0, ne, chunk):
         rows = np.arange(r0, min(ne, r0 + chunk))
-        z = zrows(mesh, rows, cdt, theta, zeta, eps, mu, G, nthreads)
+        z = zrows(mesh, rows, cdt, theta, zeta, eps, mu, G, nthreads, cfie=cfie)
         Z[:, rows, :] = z.transpose(2, 0, 1)
     return Z
 
@@ -183,13 +198,13 @@ def gram(mesh: Mesh, pi, pj):
     return out
 
 
-def tri_integrals(x, tri3, cdt, dt, zeta, g0, ng, self_term=False):
+def tri_integrals(x, tri3, cdt, dt, zeta, g0, ng, self_term=False, kd=1.0):
     """Kernel integrals over one triangle for one field point, lags g0..g0+ng-1.
     Returns array [ng, 9]: as, phis, ps, av(3), pv(3)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     t = np.ascontiguousarray(tri3, dtype=np.float64).reshape(9)
     out = np.zeros((ng, 9))
-    lib().orc_tri_integrals(_p(x), _p(t), int(self_term), cdt, dt, zeta, g0, ng, _p(out))
+    lib().orc_tri_integrals(_p(x), _p(t), int(self_term), cdt, dt, zeta, kd, g0, ng, _p(out))
     return out
 
 
@@ -197,13 +212,14 @@ def bspline(which, tau):
     return lib().orc_bspline(int(which), float(tau))
 
 
-def vinc(mesh: Mesh, pulse, t, theta, zeta, eps=None, mu=None):
+def vinc(mesh: Mesh, pulse, t, theta, zeta, eps=None, mu=None, cfie=1):
     """Tested incident field V_i at time t for one pulse (Eq. v_i)."""
     eps, mu = material(eps, mu)
+    kd, zeta = cfie_weights(cfie, zeta)
     pa = np.ascontiguousarray(pulse.as_array() if hasattr(pulse, "as_array") else pulse, dtype=np.float64)
     out = np.zeros(mesh.ne)
     lib().orc_vinc(_p(mesh.xyz), _p(mesh.tri), _p(mesh.etri), _p(mesh.efree), _p(mesh.elen),
-                   mesh.ne, _p(pa), eps, mu, theta, zeta, float(t), _p(out))
+                   mesh.ne, _p(pa), eps, mu, theta, zeta, kd, float(t), _p(out))
     return out
 
 
@@ -239,6 +255,6 @@ def history_dense(Z, J, alpha):
     return out
 
 
-def incident_all(mesh: Mesh, pulse, dt, nt, theta, zeta, eps=None, mu=None):
+def incident_all(mesh: Mesh, pulse, dt, nt, theta, zeta, eps=None, mu=None, cfie=1):
     """V^{alpha-1} for alpha = 1..nt-1 evaluated at t_alpha = alpha dt."""
-    return np.stack([vinc(mesh, pulse, a * dt, theta, zeta, eps, mu) for a in range(1, nt)])
+    return np.stack([vinc(mesh, pulse, a * dt, theta, zeta, eps, mu, cfie=cfie) for a in range(1, nt)])

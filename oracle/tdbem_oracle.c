@@ -17,6 +17,12 @@
  *    limit of n x P, inward normal) which contributes
  *    1/2 theta eta Gram_ij (1/dt + zeta/2) at g = 1 and
  *    1/2 theta eta Gram_ij (-1/dt + zeta/2) at g = 2;
+ *  - the CFIE variants of Section 4.3.1 through the weights (kd, zeta) of
+ *    the MFIE's time derivative and of the MFIE itself: CFIE1 = (1, zeta) is
+ *    Eq. cfie, CFIE2 (d/dt EFIE + d/dt MFIE) = (1, 0), CFIE3 (d/dt EFIE +
+ *    MFIE) = (0, zeta); kd multiplies every term the time derivative of the
+ *    MFIE produces (B'/dt in the P kernel, 1/dt in the identity term, dH/dt
+ *    in the incident field);
  *  - the tested incident field V_i^{alpha-1} (Eq. v_i);
  *  - the history sum sum_{g>=2} Zt^(g) J^{alpha-g} (Eq. R).
  *
@@ -115,11 +121,11 @@ static void gl_init(void) {
 /* For lag g, tau_g(r) = g - r/(c dt).  The three radial antiderivatives used:
  *   Qa(r)   = int B''(tau_g) dr = -c dt B'(tau_g)          (A-dd kernel, Eq. def_A)
  *   Qphi(r) = int B(tau_g) dr   = -c dt Bint(tau_g)        (phi-dot kernel, Eq. def_phi)
- *   Qp(r)   = F(tau_g)/r,  F = B'(tau_g)/dt + zeta B(tau_g) (P-dot + zeta P, Eq. def_P)
+ *   Qp(r)   = F(tau_g)/r,  F = kd B'(tau_g)/dt + zeta B(tau_g) (kd P-dot + zeta P, Eq. def_P)
  * They satisfy d/dr Qa = B'', d/dr Qphi = B, and (1/r) d/dr Qp = psi where
  * grad_y [F/r] = (y - x) psi(r). */
 typedef struct {
-    double cdt, dt, zeta;
+    double cdt, dt, zeta, kd;
     int g0, ng;            /* lags g0 .. g0+ng-1 */
 } kpar_t;
 
@@ -136,7 +142,7 @@ static void radial_q(const kpar_t *k, int ia, int ib, double r, double *qa, doub
         double tau = (k->g0 + i) - r / k->cdt;
         qa[i] = -k->cdt * bs1(tau);
         qphi[i] = -k->cdt * bsm1(tau);
-        qp[i] = (bs1(tau) / k->dt + k->zeta * bs0(tau)) / r;
+        qp[i] = (k->kd * bs1(tau) / k->dt + k->zeta * bs0(tau)) / r;
     }
 }
 
@@ -376,11 +382,11 @@ static void tri_integrals(const double *x, const double P[3][3], int self, const
 /* exported for pin tests: integrals of the kernels for one field point and
  * triangle.  out layout per lag: [as, phis, ps, av0, av1, av2, pv0, pv1, pv2] */
 void orc_tri_integrals(const double *x, const double *tri9, int self, double cdt, double dt,
-                       double zeta, int g0, int ng, double *out) {
+                       double zeta, double kd, int g0, int ng, double *out) {
     gl_init();
     double P[3][3];
     for (int a = 0; a < 3; ++a) for (int c = 0; c < 3; ++c) P[a][c] = tri9[3 * a + c];
-    kpar_t k = { cdt, dt, zeta, g0, ng };
+    kpar_t k = { cdt, dt, zeta, kd, g0, ng };
     acc_t acc[NGMAX];
     tri_integrals(x, P, self, &k, acc);
     for (int i = 0; i < ng; ++i) {
@@ -418,7 +424,7 @@ static void quad_points(const double P[3][3], double X[3][3]) {
 
 /* J-form coefficients for a list of (i, j) pairs; out[p*G + g], g = 0..G-1 (g=0 unused). */
 void orc_zpairs(const double *xyz, const int *tri, const int *etri, const int *efree, const double *elen,
-                double cdt, double eps, double mu, double theta, double zeta,
+                double cdt, double eps, double mu, double theta, double zeta, double kd,
                 long npairs, const int *pi, const int *pj, int G, double *out, int nthreads) {
     gl_init();
     mesh_t M = { xyz, tri, etri, efree, elen };
@@ -467,7 +473,7 @@ void orc_zpairs(const double *xyz, const int *tri, const int *etri, const int *e
                     if (g0 < 1) g0 = 1;
                     if (g1 > G - 1) g1 = G - 1;
                     if (g1 < g0) continue;
-                    kpar_t kp = { cdt, dt, zeta, g0, g1 - g0 + 1 };
+                    kpar_t kp = { cdt, dt, zeta, kd, g0, g1 - g0 + 1 };
                     tri_integrals(x, Pj, ti == tj, &kp, acc);
                     double fi[3]; sub3(x, oi, fi); fi[0] *= si; fi[1] *= si; fi[2] *= si;
                     double xo[3]; sub3(x, oj, xo);
@@ -490,7 +496,7 @@ void orc_zpairs(const double *xyz, const int *tri, const int *etri, const int *e
             }
         }
         free(acc);
-        /* identity part of the MFIE: 1/2 theta eta Gram_ij (dN/dt + zeta N)(t_alpha) */
+        /* identity part of the MFIE: 1/2 theta eta Gram_ij (kd dN/dt + zeta N)(t_alpha) */
         double gram = 0.0;
         for (int rho = 0; rho < 2; ++rho)
             for (int sg = 0; sg < 2; ++sg) {
@@ -509,8 +515,8 @@ void orc_zpairs(const double *xyz, const int *tri, const int *etri, const int *e
                 }
             }
         if (gram != 0.0 && G > 2) {
-            z[1] += 0.5 * theta * eta * gram * (1.0 / dt + 0.5 * zeta);
-            z[2] += 0.5 * theta * eta * gram * (-1.0 / dt + 0.5 * zeta);
+            z[1] += 0.5 * theta * eta * gram * (kd / dt + 0.5 * zeta);
+            z[2] += 0.5 * theta * eta * gram * (-kd / dt + 0.5 * zeta);
         }
     }
 }
@@ -520,7 +526,7 @@ void orc_zpairs(const double *xyz, const int *tri, const int *etri, const int *e
  * source triangle) so that each inner integral is evaluated once per row. */
 void orc_zrows(const double *xyz, const int *tri, int ntri, const int *etri, const int *efree,
                const double *elen, int ne, const int *tedge /* [ntri][3] edge ids */,
-               double cdt, double eps, double mu, double theta, double zeta,
+               double cdt, double eps, double mu, double theta, double zeta, double kd,
                int nrows, const int *rows, int G, double *out, int nthreads, int terms) {
     /* terms: bit 0 vector potential, bit 1 scalar potential, bit 2 magnetic
      * potential, bit 3 MFIE identity (Gram) term; 15 = the full operator */
@@ -566,7 +572,7 @@ void orc_zrows(const double *xyz, const int *tri, int ntri, const int *etri, con
                 if (g0 < 1) g0 = 1;
                 if (g1 > G - 1) g1 = G - 1;
                 if (g1 < g0) continue;
-                kpar_t kp = { cdt, dt, zeta, g0, g1 - g0 + 1 };
+                kpar_t kp = { cdt, dt, zeta, kd, g0, g1 - g0 + 1 };
                 tri_integrals(x, Pj, ti == tj, &kp, acc);
                 double fi[3]; sub3(x, oi, fi); fi[0] *= si; fi[1] *= si; fi[2] *= si;
                 double wq = Ai / 3.0;
@@ -621,8 +627,8 @@ void orc_zrows(const double *xyz, const int *tri, int ntri, const int *etri, con
                     }
                 }
             if (gram != 0.0 && G > 2 && (terms & 8)) {
-                o[(size_t)j * G + 1] += 0.5 * theta * eta * gram * (1.0 / dt + 0.5 * zeta);
-                o[(size_t)j * G + 2] += 0.5 * theta * eta * gram * (-1.0 / dt + 0.5 * zeta);
+                o[(size_t)j * G + 1] += 0.5 * theta * eta * gram * (kd / dt + 0.5 * zeta);
+                o[(size_t)j * G + 2] += 0.5 * theta * eta * gram * (-kd / dt + 0.5 * zeta);
             }
         }
     }
@@ -681,9 +687,9 @@ static void pulse_wave(const double *pl, double tau, double *g, double *gd) {
     }
 }
 
-/* V_i^{alpha-1}: tested  -dE/dt + theta eta n x (dH/dt + zeta H)  at t = t_alpha (Eq. v_i). */
+/* V_i^{alpha-1}: tested  -dE/dt + theta eta n x (kd dH/dt + zeta H)  at t = t_alpha (Eq. v_i). */
 void orc_vinc(const double *xyz, const int *tri, const int *etri, const int *efree, const double *elen,
-              int ne, const double *pulse, double eps, double mu, double theta, double zeta,
+              int ne, const double *pulse, double eps, double mu, double theta, double zeta, double kd,
               double t, double *out) {
     mesh_t M = { xyz, tri, etri, efree, elen };
     double cl = 1.0 / sqrt(eps * mu), eta = sqrt(mu / eps);
@@ -707,7 +713,7 @@ void orc_vinc(const double *xyz, const int *tri, const int *etri, const int *efr
                 double Ed[3], Hs[3], nxH[3];
                 for (int c = 0; c < 3; ++c) {
                     Ed[c] = E0 * pp[c] * gd;
-                    Hs[c] = E0 * kxp[c] / eta * (gd + zeta * g);
+                    Hs[c] = E0 * kxp[c] / eta * (kd * gd + zeta * g);
                 }
                 cross3(n, Hs, nxH);
                 double f[3]; sub3(X[q], o, f);

@@ -77,6 +77,7 @@ def test_near_far_partition_covers_all_pairs_once():
 # polynomial kernels in (r^2, tau): degree 2 in every coordinate, 2 in time
 P0 = (0.3, -0.7, 1.1, 0.45, 0.2)
 P1 = (-0.4, 0.25, 0.6, -0.3, 0.5)
+P2 = (0.15, 0.35, -0.8, 0.25, -0.6)
 
 
 def _poly(cf):
@@ -112,14 +113,43 @@ def test_hermite_interpolant_properties():
     assert np.abs(chi_fd(p, x)[0] @ w**3 - x**3).max() > 1e-3
 
 
-@pytest.mark.parametrize("interp_t,widen", [("lagrange", False), ("chi", False), ("chi", True)])
-def test_polynomial_kernel_exactness(interp_t, widen):
+@pytest.mark.parametrize("p", [4, 6])
+def test_second_derivatives_of_the_temporal_interpolants(p):
+    """l_n'': exact for quadratics (both interpolants; CHI-FD reproduces
+    quadratics, so its piecewise-linear second derivative is their constant
+    second derivative), for polynomials of degree p-1 (Lagrange), and the
+    central difference of l_n' away from the CHI-FD nodes."""
+    from oracle.ifmm import chi_fd, chi_fd_d2, lagrange, lagrange_d2, nodes
+    w = nodes(p)
+    x = np.linspace(-1.1, 1.1, 53) + 1e-3
+    c = [0.3, -1.2, 0.7]
+    f = c[0] + c[1] * w + c[2] * w ** 2
+    assert np.allclose(chi_fd_d2(p, x) @ f, 2 * c[2], atol=1e-11)
+    assert np.allclose(lagrange_d2(p, x) @ f, 2 * c[2], atol=1e-11)
+    fp = w ** (p - 1)
+    assert np.allclose(lagrange_d2(p, x) @ fp, (p - 1) * (p - 2) * x ** (p - 3), atol=1e-10)
+    h = 1e-6
+    for d2, d1 in ((chi_fd_d2, chi_fd), (lagrange_d2, lagrange)):
+        num = (d1(p, x + h)[1] - d1(p, x - h)[1]) / (2 * h)
+        assert np.allclose(d2(p, x), num, atol=1e-4)
+
+
+@pytest.mark.parametrize("interp_t,widen,cfie,dt2", [("lagrange", False, 1, "split"), ("chi", False, 1, "split"),
+                                                   ("chi", True, 1, "split"), ("chi", False, 2, "kernel"),
+                                                   ("lagrange", False, 3, "interp"), ("chi", False, 3, "interp")])
+def test_polynomial_kernel_exactness(interp_t, widen, cfie, dt2):
+    """The CFIE variants weight the magnetic channels' target derivative
+    (kd, kz) = (1, zeta), (1, 0), (0, zeta); the second time derivative of the
+    vector potential sits on kernel and interpolant (split: kernel P1 with
+    d/dt of the interpolant), on the kernel (P2 with the interpolant itself)
+    or on the interpolant (P0 with its second derivative, 2 a3)."""
     v, f = icosphere(2)
     m = O.Mesh(v, f)
     dt = 0.03 / C0
     theta, zeta = 1.0, C0 / 2
-    F = IFMM(m, dt, theta, zeta, EPS0, MU0, leaf_max=6, kernels=(_poly(P1), _poly(P0)), interp_t=interp_t,
-             widen=widen)
+    F = IFMM(m, dt, theta, zeta, EPS0, MU0, leaf_max=6, kernels=(_poly(P1), _poly(P0), _poly(P2)),
+             interp_t=interp_t, widen=widen, cfie=cfie, dt2=dt2)
+    kd, kz = {1: (1.0, zeta), 2: (1.0, 0.0), 3: (0.0, zeta)}[cfie]
     assert (F.delta > 0) == widen
     H = F.H
     assert H.lmax >= 3 and H.Mt[H.lmax] >= 3
@@ -138,6 +168,7 @@ def test_polynomial_kernel_exactness(interp_t, widen):
     sc = (C0 * dt) ** -2
     a0, a1, a2, a3, a4 = P0
     b0, b1, b2, b3, b4 = P1
+    c0, c1, c2, c3, c4 = P2
     targets = list(range(0, m.ne, 29))
     ref = np.zeros((nb + 1, len(targets)))
     avec = np.arange(1, nb + 2)
@@ -173,9 +204,15 @@ def test_polynomial_kernel_exactness(interp_t, widen):
             # vector potential: (mu/4pi) f_i.f_j d/dt[dU-kernel]; scalar: -div_i (-1/4 pi eps) div_j U-kernel;
             # magnetic: grad_y (d/dt + zeta) K0 = (2 a4 + zeta (2 a1 + 2 a4 tau)) (y - x)
             T = TAU
-            tot = sc * (MU0 / (4 * math.pi) * ((b2 + 2 * b3 * T) * Sff + b4 * Sffr)
+            if dt2 == "split":
+                vec = (b2 + 2 * b3 * T) * Sff + b4 * Sffr
+            elif dt2 == "kernel":
+                vec = (c0 + c2 * T + c3 * T * T) * Sff + (c1 + c4 * T) * Sffr
+            else:
+                vec = 2 * a3 * Sff + 0.0 * T
+            tot = sc * (MU0 / (4 * math.pi) * vec
                         + 1.0 / (4 * math.pi * EPS0) * ((a0 + a2 * T + a3 * T * T) * Sdd + (a1 + a4 * T) * Sddr)
-                        + (2 * a4 + zeta * (2 * a1 + 2 * a4 * T)) * SP)
+                        + (kd * 2 * a4 + kz * (2 * a1 + 2 * a4 * T)) * SP)
             mask = bvec[None, :] < ((avec[:, None] - 1) // M) * M            # earlier intervals at level l
             ref[:, ti] += (tot * mask) @ Jh[:, j]
     got = far[:, targets]

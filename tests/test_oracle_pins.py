@@ -404,3 +404,61 @@ def test_incident_uniform_field_limit():
             fint = k * m.area[t_] * (m.centroid[t_] - o)
             ref += fint @ (-Ed) + theta * ETA0 * fint @ np.cross(-m.n_out[t_], H)
         assert abs(V[i] - ref) < 1e-7 * abs(ref) + 1e-15
+
+
+# ------------------------------------------------------- CFIE variants (Section 4.3.1)
+def test_cfie_variants_are_the_weighted_parts():
+    """CFIE1 = dt EFIE + dt MFIE + MFIE, CFIE2 drops the MFIE, CFIE3 its time
+    derivative: the operators and the incident fields are linear in those two
+    weights, so CFIE1 = CFIE2 + CFIE3 - EFIE part (vector + scalar potential)."""
+    from paper_2303_05006_amd.inputs import gaussian_pulse
+    m = O.Mesh(*icosphere(1))
+    z = {c: O.zrows(m, [5, 61], 0.12, 1.0, C0 / 2, cfie=c) for c in (1, 2, 3)}
+    efie = O.zrows(m, [5, 61], 0.12, 1.0, C0 / 2, terms=3)
+    assert np.abs(z[1] - (z[2] + z[3] - efie)).max() <= 1e-13 * np.abs(z[1]).max()
+    assert np.abs(z[2] - z[1]).max() > 1e-3 * np.abs(z[1]).max()
+    p = gaussian_pulse(60e6, 40e6)
+    v = {c: O.vinc(m, p, 2.5e-8, 1.0, C0 / 2, cfie=c) for c in (1, 2, 3)}
+    ve = O.vinc(m, p, 2.5e-8, 0.0, C0 / 2)
+    assert np.abs(v[1] - (v[2] + v[3] - ve)).max() <= 1e-13 * np.abs(v[1]).max()
+
+
+@pytest.mark.parametrize("mesh", ["ico1", "cube2"])
+def test_cfie_time_derivative_part_first_lag_moment(mesh):
+    """The MFIE's time-derivative part alone (CFIE2's magnetic and identity
+    terms: kernel B'(tau_g)/(dt r), identity 1/2 theta eta Gram (+1/dt, -1/dt) at
+    g = 1, 2) has zero lag sum and first lag moment -1/dt times the static
+    operator, because sum_g g B'(g - x) = -1 (B reproduces linear functions):
+    sum_g g Zt^(g) = -(1/dt) [theta eta (n x static Biot-Savart part) + 1/2 theta eta Gram]."""
+    m = O.Mesh(*(icosphere(1) if mesh == "ico1" else cube(2, 2.0)))
+    cdt = 0.12
+    dt = cdt / C0
+    theta = 1.0
+    rows = [3, 40]
+    Z = O.zrows(m, rows, cdt, theta, C0 / 2, terms=12, cfie=2)
+    g = np.arange(Z.shape[2], dtype=float)
+    assert np.abs(Z.sum(axis=2)).max() <= 1e-10 * np.abs(Z).max()
+    mom = (Z * g[None, None, :]).sum(axis=2)
+    for ri, i in enumerate(rows):
+        for j in range(0, m.ne, 4):
+            ref = 0.0
+            for rho in (0, 1):
+                ti = m.etri[i, rho]
+                X, W = m.quad_points(ti)
+                n_in = -m.n_out[ti]
+                for x, w in zip(X, W):
+                    fi, divi = m.rwg(i, rho, x)
+                    for sg in (0, 1):
+                        tj = m.etri[j, sg]
+                        P = m.xyz[m.tri[tj]]
+                        _, g_pot = static_potentials(x, P)
+                        if ti == tj:
+                            nrm = m.n_out[tj]
+                            g_pot = g_pot - (g_pot @ nrm) * nrm
+                        _, divj = m.rwg(j, sg, x)
+                        oj = m.xyz[m.efree[j, sg]]
+                        Pv = divj / 2 / (4 * math.pi) * np.cross(x - oj, g_pot)
+                        ref += w * theta * ETA0 * fi @ np.cross(n_in, Pv)
+            ref += 0.5 * theta * ETA0 * O.gram(m, [i], [j])[0]
+            ref *= -1.0 / dt
+            assert abs(mom[ri, j] - ref) < 1e-10 * np.abs(mom[ri]).max(), (i, j, mom[ri, j], ref)
