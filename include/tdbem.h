@@ -45,12 +45,12 @@ extern "C" {
 
 enum {
     TDBEM_OK = 0,
-    TDBEM_EINVAL = -1,      /* invalid argument or mesh */
+    TDBEM_EINVAL = -1,      /* invalid argument, mesh or configuration */
     TDBEM_ENOMEM = -2,      /* device or host allocation failed */
     TDBEM_EHIP = -3,        /* a HIP runtime call failed */
-    TDBEM_EBREAKDOWN = -4,  /* time hierarchy breaks down (steps per interval < 3, Remark 1) */
-    TDBEM_ENOCONV = -5,     /* GMRES did not reach the tolerance within the iteration cap */
-    TDBEM_EUNSTABLE = -6    /* current norm grew beyond the configured bound */
+    TDBEM_EBREAKDOWN = -4,  /* time hierarchy breaks down: no step per finest interval (M_t = 0, Remark 1 of Section 3.4.1) */
+    TDBEM_ENOCONV = -5,     /* GMRES did not reach the tolerance within the iteration cap (Section 2.5) */
+    TDBEM_EUNSTABLE = -6    /* late-time growth of the current beyond cfg.growth_limit (Section 4.3) */
 };
 
 enum { TDBEM_MODE_DIRECT = 0, TDBEM_MODE_IFMM = 1 };
@@ -58,9 +58,11 @@ enum { TDBEM_MODE_DIRECT = 0, TDBEM_MODE_IFMM = 1 };
  * the right-hand side are FP64 in every form).  FP64: everything FP64.  FP32:
  * near-field coefficients stored in FP32, M2L operator and products in FP32 on
  * the matrix cores (moments and local expansions FP64).  BF16: near-field
- * coefficients stored in bf16 (FP64 sums), M2L as in FP32; the far field's
- * undifferentiated kernels cancel over the window, which amplifies rounding by
- * about (window steps)^2, so bf16 is not offered for the M2L. */
+ * coefficients stored in bf16 (FP64 sums); M2L operator and moments rounded to
+ * bf16 with FP32 accumulation on the matrix cores.  The far field applies the
+ * undifferentiated kernels to differenced currents; the window's terms cancel
+ * down to the retarded potential, which amplifies rounding by about (window
+ * steps)^2: the reduced forms are options whose error is measured. */
 enum { TDBEM_FP64 = 0, TDBEM_FP32 = 1, TDBEM_BF16 = 2 };
 /* Interpolants on p equispaced nodes (Section 3.2).  LAGRANGE: Lagrange
  * polynomials in space and time.  CHI_TIME: Lagrange in space; in time the
@@ -70,17 +72,33 @@ enum { TDBEM_FP64 = 0, TDBEM_FP32 = 1, TDBEM_BF16 = 2 };
  * the late-time march stable where the Lagrange variant is not. */
 enum { TDBEM_INTERP_LAGRANGE = 0, TDBEM_INTERP_CHI_TIME = 1 };
 enum { TDBEM_GUESS_EXTRAP = 0, TDBEM_GUESS_LEARNED = 1 };
-
-/* Environment switches read by tdbem_setup (IFMM mode):
- *   TDBEM_BOX_WIDEN=1     interpolation boxes = cells widened by the largest
- *                         per-axis reach of a basis support beyond its edge
- *                         midpoint (no extrapolation of the interpolants; for
- *                         bodies whose finest cells are not much larger than
- *                         their edges, e.g. structured cubes, whose march
- *                         otherwise grows after the pulse);
- *   TDBEM_CAUSAL_GUARD=1  steps per interval from the cell side minus twice
- *                         that reach, so that no far pair can interact within
- *                         one interval (Remark 1 takes the cell side alone). */
+/* The CFIE (Section 2.1, Eq. cfie; variants of Section 4.3.1):
+ *   CFIE1 = dt EFIE + theta eta (dt MFIE + zeta MFIE)   (the paper's choice),
+ *   CFIE2 = dt EFIE + theta eta dt MFIE,
+ *   CFIE3 = dt EFIE + theta eta zeta MFIE.
+ * The variant weights every term of the MFIE's time derivative (kernel, the
+ * identity term, the incident magnetic field) and of the MFIE itself. */
+enum { TDBEM_CFIE1 = 1, TDBEM_CFIE2 = 2, TDBEM_CFIE3 = 3 };
+/* Where the far field puts the second time derivative of the vector potential
+ * (Section 4.3.2): SPLIT differentiates kernel and target interpolant once
+ * each (dU/dt with l_m', Eq. ddotA_fmm, the paper's choice); KERNEL
+ * interpolates d^2U/dt^2 = c^2 d (d - 1) U^{d-2} (with l_m); INTERP
+ * interpolates U and differentiates the interpolant twice (l_m''). */
+enum { TDBEM_DT2_SPLIT = 0, TDBEM_DT2_KERNEL = 1, TDBEM_DT2_INTERP = 2 };
+/* M2L kernels (Section 3.6.1): AUTO, the operator tables of p = 4 in LDS on the
+ * matrix cores (and the generic kernel for p = 6, 8); GENERIC, the dense M2L
+ * for any p with the operator entries formed per lane from lattice distances
+ * (the same products; slower at p = 4, where it checks the tuned kernel); FFT,
+ * the M2L as a 4-D convolution evaluated in the Fourier domain (the node
+ * lattice makes every operator a function of node-index differences, Section
+ * 3.6.1, last paragraph): transformed kernels per offset and lag are set up
+ * once, each interval's moments are transformed once, products are diagonal.
+ * FFT computes in FP64 (precision must be TDBEM_FP64) and holds (2p)^3 (p+1)
+ * complex values per moment vector (20x the dense moments at p = 4). */
+enum { TDBEM_M2L_AUTO = 0, TDBEM_M2L_GENERIC = 1, TDBEM_M2L_FFT = 2 };
+/* Z0 solver (Section 2.5): DEVICE, one cooperative kernel per step for every
+ * right-hand side; HOST, the same GMRES driven from the host (reference). */
+enum { TDBEM_SOLVER_DEVICE = 0, TDBEM_SOLVER_HOST = 1 };
 
 typedef struct tdbem_ctx tdbem_ctx;
 
@@ -92,23 +110,52 @@ typedef struct {
     const int32_t *tri;       /* host [n_triangles][3], counter-clockwise seen from outside */
 } tdbem_mesh;
 
+/* Configuration.  A zero-initialised struct is not valid: dt, eps, mu,
+ * n_quad, n_rhs and the solver fields must be set (the Python binding gives
+ * the paper's defaults). */
 typedef struct {
+    /* time discretisation (Section 2.2) */
     double dt;                /* time step [s] */
     int32_t nt;               /* number of time steps the context may march */
     int32_t d;                /* temporal B-spline order; must be 2 */
+    /* medium and equation (Section 2.1) */
     double eps, mu;           /* permittivity [F/m], permeability [H/m] */
     double theta, zeta;       /* CFIE coupling constants (zeta in 1/s) */
-    int32_t p_s, p_t;         /* interpolation points per axis in space and in time (IFMM) */
-    int32_t interp;           /* TDBEM_INTERP_LAGRANGE or TDBEM_INTERP_CHI_TIME (IFMM) */
-    int32_t leaf_max;         /* subdivide a cell while it holds more edges than this */
+    int32_t cfie;             /* TDBEM_CFIE1 | TDBEM_CFIE2 | TDBEM_CFIE3 */
+    /* testing (Section 2.4) */
+    int32_t n_quad;           /* points of the triangle rule of testing and of the far-field weights: 3 */
+    /* far field (Section 3; IFMM mode) */
+    int32_t p_s, p_t;         /* interpolation points per axis in space and in time: p_s = p_t = 4, 6 or 8
+                                 (FAST4/6/8 of Section 4.2) */
+    int32_t interp;           /* TDBEM_INTERP_LAGRANGE or TDBEM_INTERP_CHI_TIME */
+    int32_t dt2;              /* TDBEM_DT2_SPLIT | TDBEM_DT2_KERNEL | TDBEM_DT2_INTERP */
+    int32_t m2l;              /* TDBEM_M2L_AUTO | TDBEM_M2L_GENERIC | TDBEM_M2L_FFT */
+    int32_t leaf_max;         /* subdivide a cell while it holds more edges than this (Section 3.4.1) */
     int32_t min_level;        /* subdivide at least down to this level (2) */
-    int32_t mu_window;        /* far-field window (paper: 8 future intervals); raised if needed */
+    int32_t mu_window;        /* future intervals of the M2L (paper: 8, Section 3.6.1); raised if needed */
+    int32_t box_widen;        /* 1: interpolation boxes = cells widened by the largest per-axis reach of a
+                                 basis support beyond its edge midpoint (no extrapolation of the
+                                 interpolants; for bodies whose finest cells are not much larger than their
+                                 edges, e.g. structured cubes); 0: the cells (the paper) */
+    int32_t causal_guard;     /* 1: steps per interval from the cell side minus twice that reach, so that no
+                                 far pair interacts within one interval; 0: the cell side (Remark 1) */
+    /* method and batch */
     int32_t mode;             /* TDBEM_MODE_DIRECT (all pairs exact) or TDBEM_MODE_IFMM */
     int32_t precision;        /* TDBEM_FP64 | TDBEM_FP32 | TDBEM_BF16 for near-field and M2L sums */
     int32_t n_rhs;            /* independent incident fields marched together */
-    double gmres_rtol;        /* relative residual tolerance of the Z0 solve */
+    /* Z0 solve (Section 2.5) */
+    double gmres_rtol;        /* relative residual tolerance */
     int32_t gmres_maxit;      /* Krylov iterations per step (cap) */
+    int32_t gmres_restart;    /* Krylov vectors per restart cycle, 1..32 */
     int32_t guess;            /* TDBEM_GUESS_EXTRAP (quadratic extrapolation) or _LEARNED */
+    int32_t solver;           /* TDBEM_SOLVER_DEVICE or TDBEM_SOLVER_HOST */
+    int32_t gmres_blocks;     /* blocks per system of the device solve (0: automatic) */
+    /* late-time stability monitor (Section 4.3): 0 disables.  Once the tested
+     * incident field of a right-hand side has fallen below 1e-6 of its largest
+     * norm so far (the excitation has passed), a step returns TDBEM_EUNSTABLE
+     * when the norm of that right-hand side's current exceeds growth_limit
+     * times the largest current norm seen while the excitation lasted. */
+    double growth_limit;
     void *stream;             /* hipStream_t for all work (NULL: the default stream) */
 } tdbem_config;
 
@@ -116,8 +163,10 @@ typedef struct {
  * on the device, FP64 semi-analytic inner integrals, 3-point testing), the Z0
  * matrix and, in IFMM mode, the interpolation tables and M2L node values
  * (Sections 2.3-2.5 and 3.4.1).  On success *out receives a new context.
- * Errors: TDBEM_EINVAL (bad mesh/config), TDBEM_EBREAKDOWN (IFMM interval of
- * fewer than 3 steps, Remark 1), TDBEM_ENOMEM, TDBEM_EHIP. */
+ * Errors: TDBEM_EINVAL (bad mesh/config, or an option not implemented:
+ * p_s = p_t in {4, 6, 8} and n_quad = 3 only), TDBEM_EBREAKDOWN (no step per finest
+ * interval, Remark 1 of Section 3.4.1, or a far-field window of more than 20
+ * intervals), TDBEM_ENOMEM, TDBEM_EHIP. */
 int tdbem_setup(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ctx **out);
 
 /* Tested incident field V^{step-1} (Eq. v_i) of n_rhs plane-wave pulses at
@@ -142,6 +191,23 @@ int tdbem_step(tdbem_ctx *ctx, const double *V_dev, double *J_dev);
 /* Restart the march at alpha = 1 with zero history. */
 int tdbem_reset(tdbem_ctx *ctx);
 
+/* Checkpoint of the marching state (Program 1: what one step hands to the
+ * next): the step counter, the ring of past currents, and in IFMM mode the
+ * moments, local expansions, pending L2L contributions and far-field
+ * potentials of every level (Programs 3-4), plus the stability monitor's
+ * running norms.  Nothing setup derives from the mesh and configuration is
+ * included.  buf NULL: *len receives the size in bytes.  Otherwise buf (host
+ * memory of at least *len bytes, owned by the caller) receives the state and
+ * *len its size; EINVAL if *len is too small.  Waits for the stream. */
+int tdbem_checkpoint(const tdbem_ctx *ctx, void *buf, size_t *len);
+
+/* Restore a checkpoint into a context set up from the same mesh and
+ * configuration (the checkpoint records the sizes and a fingerprint of both;
+ * EINVAL if they differ or the buffer is malformed).  The march then
+ * continues bitwise as the checkpointed context would have.  buf: host
+ * memory of len bytes, read only. */
+int tdbem_restore(tdbem_ctx *ctx, const void *buf, size_t len);
+
 enum {
     TDBEM_Q_NE = 0,          /* int64: number of edges */
     TDBEM_Q_EDGES = 1,       /* int32 [N_e][2]: (lo, hi) vertex ids in canonical order */
@@ -152,7 +218,7 @@ enum {
     TDBEM_Q_Z0_NNZ = 6,      /* int64: non-zeros of Zt^(1) */
     TDBEM_Q_NCELLS = 7,      /* int32 [l_max+1]: cells per level */
     TDBEM_Q_NILIST = 8,      /* int64 [l_max+1]: interaction-list entries per level */
-    TDBEM_Q_WINDOW = 9,      /* int32: far-field source intervals per M2L (mu + 1) */
+    TDBEM_Q_WINDOW = 9,      /* int32: largest number of far-field source intervals per M2L over the levels */
     TDBEM_Q_GMRES_ITERS = 10,/* int32: Krylov iterations of the last step (max over rhs) */
     TDBEM_Q_DEVICE_BYTES = 11,/* int64: device memory held by the context */
     TDBEM_Q_STEP = 12,       /* int32: next step alpha */
@@ -160,7 +226,15 @@ enum {
     TDBEM_Q_SETUP_MS = 14,   /* double: wall time of tdbem_setup */
     TDBEM_Q_PHASE_MS = 15,   /* double [TDBEM_NPHASE]: device time per phase since profiling was enabled */
     TDBEM_Q_PHASE_COUNT = 16, /* int64 [TDBEM_NPHASE]: timed launches per phase */
-    TDBEM_Q_GUESS_USED = 17  /* int64: (step, rhs) pairs whose solve started from the learned guess */
+    TDBEM_Q_GUESS_USED = 17, /* int64: (step, rhs) pairs whose solve started from the learned guess */
+    TDBEM_Q_CONFIG = 18,     /* tdbem_config: the configuration as set up (the switches in effect) */
+    TDBEM_Q_D0_NNZ = 19,     /* int64: non-zero coefficients (i, j, g >= 1) of the discretised problem over
+                                all pairs (the exact lag support of every pair, as the direct mode stores
+                                it); computed on the device at the first query */
+    TDBEM_Q_UNSTABLE = 20,   /* int32 [n_rhs]: 1 where the stability monitor has tripped */
+    TDBEM_Q_WINDOWS = 21     /* int32 [l_max+1]: source intervals per M2L per level, mu + ceil(3 / M_t(l)) (0 above
+                                level 2): the window's oldest ceil(3 / M_t) intervals use differences truncated at
+                                the oldest interval's start */
 };
 
 /* Phases timed by tdbem_profile (HIP events on the work stream around each

@@ -98,11 +98,14 @@ def lagrange_d2(p, xi):
 
 
 def chi_fd_d2(p, xi):
-    """Second derivatives of the CHI-FD cardinal functions (piecewise linear)."""
+    """Second derivatives of the CHI-FD cardinal functions: piecewise linear
+    and discontinuous at the interior nodes.  At a node (within 1e-9 of a
+    segment) the segment on its left is taken, i.e. the limit from the past;
+    target steps fall on nodes whenever (p - 1) q / M_t is an integer."""
     w = nodes(p)
     h = w[1] - w[0]
     xi = np.asarray(xi, float)
-    seg = np.clip(np.floor((xi + 1.0) / h).astype(int), 0, p - 2)
+    seg = np.clip(np.ceil((xi + 1.0) / h - 1e-9).astype(int) - 1, 0, p - 2)
     t = (xi - w[seg]) / h
     ddH = [12 * t - 6, 6 * t - 4, -12 * t + 6, 6 * t - 2]
     out = np.zeros(xi.shape + (p,))
@@ -421,16 +424,23 @@ class IFMM:
             for off, prs in groups.items():
                 O_idx = np.array([p_[0] for p_ in prs])
                 S_idx = [p_[1] for p_ in prs]
-                src = np.stack([MM[(l, si)].reshape(-1, 7, nn) for si in S_idx])   # [pairs, KS, 7, nn]
-                KS = src.shape[1]
+                # sources interval-major, channel groups apart: [KS, pairs, channels, nn]
+                src = np.stack([MM[(l, si)].reshape(-1, 7, nn) for si in S_idx], axis=1)
+                KS, np_ = src.shape[0], src.shape[1]
+                srcA = np.ascontiguousarray(src[:, :, 0:3])
+                srcP = np.ascontiguousarray(src[:, :, 3:7])
+                YA = np.zeros((KT, np_, 3, nn))             # this offset's contributions per pair
+                YP = np.zeros((KT, np_, 4, nn))
                 for lag in range(1, KT):
                     n_k = min(KT - lag, KS)
                     if n_k <= 0:
                         continue
                     K1, K0 = self._m2l_offset(l, np.array(off), lag)
-                    x = src[:, :n_k]
-                    LC[O_idx, lag:lag + n_k, 0:3] += x[:, :, 0:3] @ K1.T
-                    LC[O_idx, lag:lag + n_k, 3:7] += x[:, :, 3:7] @ K0.T
+                    # the products of every (interval, pair, channel) as one matrix product each
+                    YA[lag:lag + n_k] += (srcA[:n_k].reshape(-1, nn) @ K1.T).reshape(n_k, np_, 3, nn)
+                    YP[lag:lag + n_k] += (srcP[:n_k].reshape(-1, nn) @ K0.T).reshape(n_k, np_, 4, nn)
+                LC[O_idx, :, 0:3] += YA.transpose(1, 0, 2, 3)
+                LC[O_idx, :, 3:7] += YP.transpose(1, 0, 2, 3)
             for oi, O in enumerate(H.levels[l]):
                 lc = LC[oi]
                 if O.leaf:

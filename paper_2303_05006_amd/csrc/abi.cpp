@@ -69,10 +69,21 @@ size_t gmres_work_doubles(const tdbem_ctx *C, int maxit);
 bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s);
 size_t gmres_coop_work_doubles(int ne, int nrhs);
 
-static GeoDev geo(const tdbem_ctx *C) {
-    return GeoDev{C->d_xyz, C->d_tri, C->d_area, C->d_nrm, C->d_qpt, C->d_etri, C->d_efree, C->d_elen,
-                  C->cdt, C->cfg.dt, C->cfg.eps, C->cfg.mu, C->cfg.theta, C->cfg.zeta, C->eta};
+// weights of the MFIE's time derivative (kd) and of the MFIE (zeta) in the
+// CFIE variants of Section 4.3.1
+void cfie_weights(const tdbem_config &cfg, double &kd, double &zeta) {
+    kd = cfg.cfie == TDBEM_CFIE3 ? 0.0 : 1.0;
+    zeta = cfg.cfie == TDBEM_CFIE2 ? 0.0 : cfg.zeta;
 }
+
+static GeoDev geo(const tdbem_ctx *C) {
+    double kd, zeta;
+    cfie_weights(C->cfg, kd, zeta);
+    return GeoDev{C->d_xyz, C->d_tri, C->d_area, C->d_nrm, C->d_qpt, C->d_etri, C->d_efree, C->d_elen,
+                  C->cdt, C->cfg.dt, C->cfg.eps, C->cfg.mu, C->cfg.theta, zeta, C->eta, kd};
+}
+
+static uint64_t fingerprint(const tdbem_ctx *C);
 
 // near pairs (leaf order), row-major; DIRECT mode: all pairs
 static void build_near_pairs(tdbem_ctx *C, std::vector<int> &pi, std::vector<int> &pj) {
@@ -124,9 +135,24 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->n_rhs >= 1 && cfg->n_rhs <= 4096, TDBEM_EINVAL, "n_rhs out of range");
     TD_REQUIRE(cfg->mode == TDBEM_MODE_DIRECT || cfg->mode == TDBEM_MODE_IFMM, TDBEM_EINVAL, "unknown mode");
     TD_REQUIRE(cfg->precision >= TDBEM_FP64 && cfg->precision <= TDBEM_BF16, TDBEM_EINVAL, "unknown precision");
+    TD_REQUIRE(cfg->cfie == TDBEM_CFIE1 || cfg->cfie == TDBEM_CFIE2 || cfg->cfie == TDBEM_CFIE3, TDBEM_EINVAL,
+               "unknown CFIE variant (TDBEM_CFIE1, _CFIE2 or _CFIE3)");
+    TD_REQUIRE(cfg->n_quad == 3, TDBEM_EINVAL, "only the interior 3-point triangle rule (n_quad = 3) is implemented");
+    TD_REQUIRE(cfg->dt2 >= TDBEM_DT2_SPLIT && cfg->dt2 <= TDBEM_DT2_INTERP, TDBEM_EINVAL,
+               "unknown placement of the second time derivative");
+    TD_REQUIRE(cfg->box_widen == 0 || cfg->box_widen == 1, TDBEM_EINVAL, "box_widen must be 0 or 1");
+    TD_REQUIRE(cfg->causal_guard == 0 || cfg->causal_guard == 1, TDBEM_EINVAL, "causal_guard must be 0 or 1");
+    TD_REQUIRE(cfg->gmres_maxit >= 1, TDBEM_EINVAL, "gmres_maxit must be positive");
+    TD_REQUIRE(cfg->gmres_restart >= 1 && cfg->gmres_restart <= 32, TDBEM_EINVAL, "gmres_restart must be in 1..32");
+    TD_REQUIRE(cfg->gmres_rtol >= 0.0, TDBEM_EINVAL, "gmres_rtol must be non-negative");
+    TD_REQUIRE(cfg->solver == TDBEM_SOLVER_DEVICE || cfg->solver == TDBEM_SOLVER_HOST, TDBEM_EINVAL, "unknown solver");
+    TD_REQUIRE(cfg->gmres_blocks >= 0 && cfg->gmres_blocks <= 256, TDBEM_EINVAL, "gmres_blocks must be in 0..256");
+    TD_REQUIRE(cfg->growth_limit >= 0.0, TDBEM_EINVAL, "growth_limit must be non-negative");
+    TD_REQUIRE(cfg->guess == TDBEM_GUESS_EXTRAP || cfg->guess == TDBEM_GUESS_LEARNED, TDBEM_EINVAL, "unknown guess");
     C->stream = (hipStream_t)cfg->stream;
-    if (const char *dbg = std::getenv("TDBEM_DEBUG_GMRES")) C->debug_gmres = dbg[0] == '1';
-    if (const char *hs = std::getenv("TDBEM_HOST_GMRES")) C->use_coop = hs[0] != '1';
+    if (const char *dbg = std::getenv("TDBEM_DEBUG_GMRES")) C->debug_gmres = dbg[0] == '1';   // trace only
+    C->use_coop = cfg->solver == TDBEM_SOLVER_DEVICE;
+    C->gmres_blocks = cfg->gmres_blocks;
     C->nrhs = cfg->n_rhs;
     C->c = 1.0 / std::sqrt(cfg->eps * cfg->mu);
     C->eta = std::sqrt(cfg->mu / cfg->eps);
@@ -281,29 +307,54 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_rhs = dalloc<double>(C, nv);
     C->d_x = dalloc<double>(C, nv);
     C->d_tmp = dalloc<double>(C, nv);
-    C->d_work = dalloc<double>(C, std::max(gmres_work_doubles(C, std::max(1, cfg->gmres_maxit)),
+    C->d_work = dalloc<double>(C, std::max(gmres_work_doubles(C, cfg->gmres_restart),
                                            gmres_coop_work_doubles(ne, C->nrhs)));
     C->d_iflag = dalloc<int>(C, 4 * (size_t)C->nrhs);
     TD_HIP(hipMemset(C->d_iflag, 0, 4 * (size_t)C->nrhs * sizeof(int)));
     C->d_gbar = dalloc<unsigned>(C, (size_t)GMRES_BAR_WORDS * C->nrhs);
     TD_HIP(hipMemset(C->d_gbar, 0, (size_t)GMRES_BAR_WORDS * C->nrhs * sizeof(unsigned)));
     TD_HIP(hipHostMalloc((void **)&C->h_iflag, 4 * (size_t)C->nrhs * sizeof(int), hipHostMallocDefault));
-    if (const char *gb = std::getenv("TDBEM_GMRES_BLOCKS")) C->gmres_blocks = std::max(1, std::atoi(gb));
+    C->d_stat = dalloc<double>(C, 2 * (size_t)C->nrhs);
+    TD_HIP(hipHostMalloc((void **)&C->h_stat, 2 * (size_t)C->nrhs * sizeof(double), hipHostMallocDefault));
+    C->mon_vmax.assign(C->nrhs, 0.0);
+    C->mon_jdrive.assign(C->nrhs, 0.0);
+    C->mon_trip.assign(C->nrhs, 0);
     C->d_scal = dalloc<double>(C, 64 * (size_t)C->nrhs);
     C->d_pulse = dalloc<double>(C, 11 * (size_t)C->nrhs);
     TD_HIP(hipMemsetAsync(C->d_Jring, 0, (size_t)ne * R * C->nrhs * sizeof(double), s));
     if (C->d_Jring32) TD_HIP(hipMemsetAsync(C->d_Jring32, 0, (size_t)ne * R * C->nrhs * sizeof(float), s));
     TD_HIP(hipStreamSynchronize(s));
     C->alpha = 1;
+    C->fingerprint = fingerprint(C);
     C->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
 static void reset_impl(tdbem_ctx *C) {
     hipStream_t s = C->stream;
+    std::fill(C->mon_vmax.begin(), C->mon_vmax.end(), 0.0);
+    std::fill(C->mon_jdrive.begin(), C->mon_jdrive.end(), 0.0);
+    std::fill(C->mon_trip.begin(), C->mon_trip.end(), 0);
     TD_HIP(hipMemsetAsync(C->d_Jring, 0, (size_t)C->ne * C->ring * C->nrhs * sizeof(double), s));
     if (C->d_Jring32) TD_HIP(hipMemsetAsync(C->d_Jring32, 0, (size_t)C->ne * C->ring * C->nrhs * sizeof(float), s));
     if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_reset(C);
     C->alpha = 1;
+}
+
+// Late-time stability monitor (Section 4.3 observes growth after the
+// excitation for some variants): per right-hand side, once the tested incident
+// field has fallen below 1e-6 of its largest norm so far, the current's norm
+// must stay within growth_limit times its largest norm during the excitation.
+static bool monitor_update(tdbem_ctx *C) {
+    bool trip = false;
+    for (int r = 0; r < C->nrhs; ++r) {
+        const double v = std::sqrt(C->h_stat[2 * r]), j = std::sqrt(C->h_stat[2 * r + 1]);
+        C->mon_vmax[r] = std::max(C->mon_vmax[r], v);
+        const bool driven = C->mon_vmax[r] > 0.0 && v > 1e-6 * C->mon_vmax[r];
+        if (driven) C->mon_jdrive[r] = std::max(C->mon_jdrive[r], j);
+        else if (j > C->cfg.growth_limit * C->mon_jdrive[r] || !std::isfinite(j)) C->mon_trip[r] = 1;
+        trip = trip || C->mon_trip[r];
+    }
+    return trip;
 }
 
 static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, const double *Jgiven) {
@@ -311,8 +362,13 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
     const int64_t nv = (int64_t)C->ne * C->nrhs;
     int a = C->alpha;
     int rc = TDBEM_OK;
+    const bool monitor = solve && C->cfg.growth_limit > 0.0;
     if (solve) {
-        { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_gather_in(C, V, C->d_rhs, s); }
+        {
+            PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
+            launch_gather_in(C, V, C->d_rhs, s);
+            if (monitor) launch_colnorm2(C, C->d_rhs, C->d_stat, 0, s);
+        }
         { PhaseScope ps(C->prof, TDBEM_PH_NEAR, s); launch_near(C, a, C->d_tmp, 1.0, s); }
         {
             PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
@@ -327,6 +383,10 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
             const int maxit = std::max(1, C->cfg.gmres_maxit);
             if (C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s)) {
                 const size_t nf = 4 * (size_t)C->nrhs;
+                if (monitor) {
+                    launch_colnorm2(C, C->d_x, C->d_stat, 1, s);
+                    TD_HIP(hipMemcpyAsync(C->h_stat, C->d_stat, 2 * C->nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+                }
                 TD_HIP(hipMemcpyAsync(C->h_iflag, C->d_iflag, nf * sizeof(int), hipMemcpyDeviceToHost, s));
                 TD_HIP(hipStreamSynchronize(s));
                 int its = 0;
@@ -343,9 +403,15 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
                 }
             } else {
                 C->last_iters = gmres_solve(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, &ok, s);
+                if (monitor) {
+                    launch_colnorm2(C, C->d_x, C->d_stat, 1, s);
+                    TD_HIP(hipMemcpyAsync(C->h_stat, C->d_stat, 2 * C->nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
+                    TD_HIP(hipStreamSynchronize(s));
+                }
             }
         }
         if (!ok) rc = TDBEM_ENOCONV;
+        if (monitor && monitor_update(C)) rc = TDBEM_EUNSTABLE;
     } else {
         launch_gather_in(C, Jgiven, C->d_x, s);
     }
@@ -354,6 +420,97 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
     if (Jout) { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_scatter_out(C, C->d_x, Jout, s); }
     C->alpha = a + 1;
     return rc;
+}
+
+void launch_count_d0(const GeoDev &G, int ne, unsigned long long *count, hipStream_t s);
+
+int64_t count_d0_nnz(const tdbem_ctx *C) {
+    unsigned long long *d = nullptr, h = 0;
+    TD_HIP(hipMalloc(&d, sizeof(unsigned long long)));
+    struct Free { void *p; ~Free() { (void)hipFree(p); } } guard{d};
+    TD_HIP(hipMemsetAsync(d, 0, sizeof(unsigned long long), C->stream));
+    launch_count_d0(geo(C), C->ne, d, C->stream);
+    TD_HIP(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, C->stream));
+    TD_HIP(hipStreamSynchronize(C->stream));
+    return (int64_t)h;
+}
+
+// FNV-1a over the mesh and every configuration field that shapes the state
+static uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+static uint64_t fingerprint(const tdbem_ctx *C) {
+    uint64_t h = 14695981039346656037ull;
+    h = fnv(h, C->H.xyz.data(), C->H.xyz.size() * sizeof(double));
+    h = fnv(h, C->H.tri.data(), C->H.tri.size() * sizeof(int));
+    const tdbem_config &c = C->cfg;
+    const double dv[] = {c.dt, c.eps, c.mu, c.theta, c.zeta, c.gmres_rtol, c.growth_limit};
+    const int32_t iv[] = {c.nt, c.d, c.cfie, c.n_quad, c.p_s, c.p_t, c.interp, c.dt2, c.m2l, c.leaf_max, c.min_level,
+                          c.mu_window, c.box_widen, c.causal_guard, c.mode, c.precision, c.n_rhs, c.gmres_maxit,
+                          c.gmres_restart, c.guess, c.solver, c.gmres_blocks};
+    h = fnv(h, dv, sizeof(dv));
+    return fnv(h, iv, sizeof(iv));
+}
+
+// checkpoint layout: header, per-rhs monitor state, current ring, FP32 ring
+// copy (reduced forms), far-field state
+struct CkptHeader {
+    char magic[8];
+    uint64_t fingerprint;
+    int64_t ne, nrhs, ring, far_bytes;
+    int32_t alpha, last_iters;
+};
+static size_t ring_bytes(const tdbem_ctx *C) { return (size_t)C->ne * C->ring * C->nrhs * sizeof(double); }
+static size_t ring32_bytes(const tdbem_ctx *C) {
+    return C->d_Jring32 ? (size_t)C->ne * C->ring * C->nrhs * sizeof(float) : 0;
+}
+static size_t far_bytes(const tdbem_ctx *C) { return C->far ? ifmm_state_bytes(C) : 0; }
+static size_t ckpt_bytes(const tdbem_ctx *C) {
+    return sizeof(CkptHeader) + (size_t)C->nrhs * (2 * sizeof(double) + sizeof(int32_t)) + ring_bytes(C) +
+           ring32_bytes(C) + far_bytes(C);
+}
+
+static void checkpoint_impl(tdbem_ctx *C, char *buf) {
+    CkptHeader hd;
+    std::memcpy(hd.magic, "TDBEMCK1", 8);
+    hd.fingerprint = C->fingerprint;
+    hd.ne = C->ne; hd.nrhs = C->nrhs; hd.ring = C->ring; hd.far_bytes = (int64_t)far_bytes(C);
+    hd.alpha = C->alpha; hd.last_iters = C->last_iters;
+    char *p = buf;
+    std::memcpy(p, &hd, sizeof(hd)); p += sizeof(hd);
+    std::memcpy(p, C->mon_vmax.data(), C->nrhs * sizeof(double)); p += C->nrhs * sizeof(double);
+    std::memcpy(p, C->mon_jdrive.data(), C->nrhs * sizeof(double)); p += C->nrhs * sizeof(double);
+    for (int r = 0; r < C->nrhs; ++r) { int32_t t = C->mon_trip[r]; std::memcpy(p, &t, 4); p += 4; }
+    hipStream_t s = C->stream;
+    TD_HIP(hipMemcpyAsync(p, C->d_Jring, ring_bytes(C), hipMemcpyDeviceToHost, s)); p += ring_bytes(C);
+    if (C->d_Jring32) { TD_HIP(hipMemcpyAsync(p, C->d_Jring32, ring32_bytes(C), hipMemcpyDeviceToHost, s)); p += ring32_bytes(C); }
+    if (C->far) ifmm_state_copy(C, p, true, s);
+    TD_HIP(hipStreamSynchronize(s));
+}
+
+static void restore_impl(tdbem_ctx *C, const char *buf, size_t len) {
+    TD_REQUIRE(len >= sizeof(CkptHeader), TDBEM_EINVAL, "checkpoint too short");
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    TD_REQUIRE(std::memcmp(hd.magic, "TDBEMCK1", 8) == 0, TDBEM_EINVAL, "not a checkpoint of this library");
+    TD_REQUIRE(hd.fingerprint == C->fingerprint && hd.ne == C->ne && hd.nrhs == C->nrhs && hd.ring == C->ring &&
+                   hd.far_bytes == (int64_t)far_bytes(C),
+               TDBEM_EINVAL, "checkpoint of another mesh or configuration");
+    TD_REQUIRE(len == ckpt_bytes(C), TDBEM_EINVAL, "checkpoint size does not match the context");
+    TD_REQUIRE(hd.alpha >= 1, TDBEM_EINVAL, "malformed checkpoint");
+    const char *p = buf + sizeof(hd);
+    std::memcpy(C->mon_vmax.data(), p, C->nrhs * sizeof(double)); p += C->nrhs * sizeof(double);
+    std::memcpy(C->mon_jdrive.data(), p, C->nrhs * sizeof(double)); p += C->nrhs * sizeof(double);
+    for (int r = 0; r < C->nrhs; ++r) { int32_t t; std::memcpy(&t, p, 4); C->mon_trip[r] = t; p += 4; }
+    hipStream_t s = C->stream;
+    TD_HIP(hipMemcpyAsync(C->d_Jring, p, ring_bytes(C), hipMemcpyHostToDevice, s)); p += ring_bytes(C);
+    if (C->d_Jring32) { TD_HIP(hipMemcpyAsync(C->d_Jring32, p, ring32_bytes(C), hipMemcpyHostToDevice, s)); p += ring32_bytes(C); }
+    if (C->far) ifmm_state_copy(C, const_cast<char *>(p), false, s);
+    TD_HIP(hipStreamSynchronize(s));
+    C->alpha = hd.alpha;
+    C->last_iters = hd.last_iters;
 }
 
 }  // namespace tdbem
@@ -391,6 +548,10 @@ int tdbem_setup(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ctx **out
         set_error("host allocation failed");
         tdbem_destroy(C);
         return TDBEM_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(std::string("setup failed: ") + e.what());
+        tdbem_destroy(C);
+        return TDBEM_EINVAL;
     }
     *out = C;
     return TDBEM_OK;
@@ -426,7 +587,27 @@ int tdbem_step(tdbem_ctx *C, const double *V, double *J) {
     int rc = TDBEM_OK;
     TD_GUARD({ rc = step_impl(C, V, J, true, nullptr); });
     if (rc == TDBEM_ENOCONV) set_error("GMRES did not reach the tolerance");
+    if (rc == TDBEM_EUNSTABLE) set_error("late-time growth: the current exceeds growth_limit times its norm during the excitation");
     return rc;
+}
+
+int tdbem_checkpoint(const tdbem_ctx *Cc, void *buf, size_t *len) {
+    if (!Cc || !len) { set_error("null argument"); return TDBEM_EINVAL; }
+    tdbem_ctx *C = const_cast<tdbem_ctx *>(Cc);
+    TD_GUARD({
+        const size_t need = ckpt_bytes(C);
+        if (!buf) { *len = need; return TDBEM_OK; }
+        TD_REQUIRE(*len >= need, TDBEM_EINVAL, "checkpoint buffer too small");
+        checkpoint_impl(C, (char *)buf);
+        *len = need;
+    });
+    return TDBEM_OK;
+}
+
+int tdbem_restore(tdbem_ctx *C, const void *buf, size_t len) {
+    if (!C || !buf) { set_error("null argument"); return TDBEM_EINVAL; }
+    TD_GUARD({ restore_impl(C, (const char *)buf, len); });
+    return TDBEM_OK;
 }
 
 int tdbem_reset(tdbem_ctx *C) {
@@ -456,6 +637,22 @@ int tdbem_query(const tdbem_ctx *C, int32_t key, void *out) {
         case TDBEM_Q_STEP: *(int32_t *)out = C->alpha; break;
         case TDBEM_Q_EDGE_LEAF: std::memcpy(out, T.iperm.data(), sizeof(int) * (size_t)C->ne); break;
         case TDBEM_Q_SETUP_MS: *(double *)out = C->setup_ms; break;
+        case TDBEM_Q_CONFIG: std::memcpy(out, &C->cfg, sizeof(tdbem_config)); break;
+        case TDBEM_Q_WINDOWS:
+            for (int l = 0; l <= T.lmax; ++l) ((int32_t *)out)[l] = l < (int)C->windows.size() ? C->windows[l] : 0;
+            break;
+        case TDBEM_Q_UNSTABLE:
+            for (int r = 0; r < C->nrhs; ++r) ((int32_t *)out)[r] = C->mon_trip[r];
+            break;
+        case TDBEM_Q_D0_NNZ:
+            try {
+                if (C->d0_nnz < 0) const_cast<tdbem_ctx *>(C)->d0_nnz = count_d0_nnz(C);
+                *(int64_t *)out = C->d0_nnz;
+            } catch (const Error &e) {
+                set_error(e.msg);
+                return e.code;
+            }
+            break;
         case TDBEM_Q_GUESS_USED:
             try {
                 *(int64_t *)out = guess_used(const_cast<tdbem_ctx *>(C));
@@ -544,6 +741,7 @@ void tdbem_destroy(tdbem_ctx *C) {
     for (void *p : C->allocs) (void)hipFree(p);
     if (C->h_scal) (void)hipHostFree(C->h_scal);
     if (C->h_iflag) (void)hipHostFree(C->h_iflag);
+    if (C->h_stat) (void)hipHostFree(C->h_stat);
     delete C;
 }
 

@@ -429,7 +429,7 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
     nbx = std::min(nbx, resident);
     if (nbx < 1 || resident < 1) return false;
     const int per_launch = std::max(1, resident / nbx);
-    const int m = std::min(GM_MAXV - 1, std::max(1, maxit));
+    const int m = std::min(GM_MAXV - 1, std::max(1, std::min(maxit, C->cfg.gmres_restart)));
     double *work = C->d_work;
     const double *bs = b;
     double *xs = x;

@@ -98,3 +98,27 @@ void launch_gather_vals(const double *val, const int64_t *idx, int64_t n, double
 }
 
 }  // namespace tdbem
+
+namespace tdbem {
+
+// number of stored coefficients of the all-pairs problem: sum over every
+// (i, j) of its exact lag range (the direct mode's storage); grid-stride over
+// pairs, integer sums (exact, order-independent)
+__global__ void __launch_bounds__(256) k_count_d0(GeoDev G, int ne, unsigned long long *count) {
+    const int64_t np = (int64_t)ne * ne;
+    unsigned long long s = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+        int lo, hi;
+        pair_lag_range(G, (int)(p / ne), (int)(p % ne), lo, hi);
+        if (hi >= lo) s += (unsigned long long)(hi - lo + 1);
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(count, s);
+}
+
+void launch_count_d0(const GeoDev &G, int ne, unsigned long long *count, hipStream_t s) {
+    hipLaunchKernelGGL(k_count_d0, dim3(2048), dim3(256), 0, s, G, ne, count);
+    TD_HIP(hipGetLastError());
+}
+
+}  // namespace tdbem

@@ -403,7 +403,7 @@ void launch_extrap(const tdbem_ctx *C, int alpha, double *x, hipStream_t s) {
 int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, bool *ok, hipStream_t s) {
     const int ne = C->ne, nr = C->nrhs;
     const int64_t n = (int64_t)ne * nr;
-    const int m = std::max(1, std::min(maxit, 30));
+    const int m = std::max(1, std::min(maxit, C->cfg.gmres_restart));
     double *V = C->d_work;                       // (m+1) vectors
     size_t vs = (size_t)n;
     double *w = V + (size_t)(m + 1) * vs;
@@ -530,11 +530,36 @@ int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit
     return total;
 }
 
-size_t gmres_work_doubles(const tdbem_ctx *C, int maxit) {
-    const int m = std::max(1, std::min(maxit, 30));
+size_t gmres_work_doubles(const tdbem_ctx *C, int restart) {
+    const int m = std::max(1, std::min(restart, 32));
     size_t n = (size_t)C->ne * C->nrhs;
     int nb = (C->ne + DOT_ROWS - 1) / DOT_ROWS;
     return (size_t)(m + 3) * n + (size_t)nb * (m + 1) * C->nrhs + 64;
+}
+
+}  // namespace tdbem
+
+namespace tdbem {
+
+// out[2 r + slot] = sum_e x[e][r]^2: one block per right-hand side, fixed
+// reduction order (the stability monitor's norms)
+__global__ void __launch_bounds__(256) k_colnorm2(int ne, int nrhs, const double *__restrict__ x, double *out, int slot) {
+    const int r = blockIdx.x;
+    __shared__ double part[4];
+    double s = 0.0;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        const double v = x[(size_t)e * nrhs + r];
+        s += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[2 * r + slot] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+void launch_colnorm2(const tdbem_ctx *C, const double *x, double *out, int slot, hipStream_t s) {
+    hipLaunchKernelGGL(k_colnorm2, dim3(C->nrhs), dim3(256), 0, s, C->ne, C->nrhs, x, out, slot);
+    TD_HIP(hipGetLastError());
 }
 
 }  // namespace tdbem

@@ -76,6 +76,7 @@ struct GeoDev {
     const double *xyz; const int *tri; const double *area; const double *nrm; const double *qpt;
     const int *etri; const int *efree; const double *elen;
     double cdt, dt, eps, mu, theta, zeta, eta;
+    double kd;   // weight of the MFIE's time derivative (CFIE1, CFIE2: 1; CFIE3: 0); zeta is 0 for CFIE2
 };
 
 struct FarState;
@@ -164,6 +165,14 @@ struct tdbem_ctx {
     unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve, GMRES_BAR_WORDS per rhs
     int gmres_blocks = 0;           // blocks per system of the cooperative solve (0: automatic)
     bool use_coop = true;           // device-resident solve
+    // late-time stability monitor: per rhs, squared norms of V and J of the
+    // step ([rhs][2], device and pinned host), largest |V| so far, largest |J|
+    // while the excitation lasted, tripped flag
+    double *d_stat = nullptr, *h_stat = nullptr;
+    std::vector<double> mon_vmax, mon_jdrive;
+    std::vector<int> mon_trip;
+    uint64_t fingerprint = 0;       // mesh and configuration, recorded in checkpoints
+    int64_t d0_nnz = -1;            // all-pairs coefficient count (computed at the first query)
 
     // host copies of the coefficient pair structure (leaf order, sorted by row)
     std::vector<int> hp_i, hp_j, hp_lo, hp_hi;
@@ -172,7 +181,8 @@ struct tdbem_ctx {
 
     // space-time hierarchy (IFMM)
     std::vector<int> Mt;            // steps per interval per level (0 for levels < 2)
-    int window = 0;                 // source intervals per M2L (mu + 1)
+    int window = 0;                 // largest number of source intervals per M2L over the levels
+    std::vector<int> windows;       // source intervals per M2L per level (mu + ceil(3 / M_t))
     int far_ring_need = 0;          // history ring length the far field needs
     tdbem::FarState *far = nullptr;
     tdbem::GuessState *guess = nullptr;   // learned initial guess (features, network)
@@ -207,6 +217,9 @@ bool guess_active(const tdbem_ctx *C);
 void launch_guess(tdbem_ctx *C, int alpha, hipStream_t s);
 int64_t guess_used(tdbem_ctx *C);
 void launch_spmv(const tdbem_ctx *C, const double *x, double *y, hipStream_t s);
+void launch_colnorm2(const tdbem_ctx *C, const double *x, double *out, int slot, hipStream_t s);
+int64_t count_d0_nnz(const tdbem_ctx *C);
+void cfie_weights(const tdbem_config &cfg, double &kd, double &zeta);
 void guess_grad(const float *P, const float *X, const float *Y, int64_t n, float *G, float *loss, hipStream_t s);
 void guess_adam(float *P, const float *G, float *M, float *V, int t, float lr, float b1, float b2, float eps,
                 hipStream_t s);

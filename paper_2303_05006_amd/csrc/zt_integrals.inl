@@ -9,7 +9,7 @@
 // closed forms in tau = g - r/(c dt):
 //   Qa   = -c dt B'(tau)       (d/dr Qa = B'')
 //   Qphi = -c dt Bint(tau)     (d/dr Qphi = B)
-//   Qp   = F(tau)/r, F = B'(tau)/dt + zeta B(tau)   ((1/r) d/dr Qp = psi, grad(F/r) = (y-x) psi)
+//   Qp   = F(tau)/r, F = kd B'(tau)/dt + zeta B(tau)   ((1/r) d/dr Qp = psi, grad(F/r) = (y-x) psi)
 // The angular integral over each edge's signed sub-triangle is taken in
 // v = asinh(s/|d|) (smooth in a strip of half-width pi/2), split where the
 // light-cone circles r = (g-k) c dt cross the edge; in-plane vector moments use
@@ -44,7 +44,7 @@ TD_HD double bsp_int(double t) {
 }
 
 struct LagK {
-    double cdt, dt, zeta;
+    double cdt, dt, zeta, kd;
     int g;
 };
 struct Q3 { double a, phi, p; };
@@ -55,7 +55,7 @@ TD_HD Q3 radial(const LagK &k, double r) {
     double b1 = bsp_d(tau);
     q.a = -k.cdt * b1;
     q.phi = -k.cdt * bsp_int(tau);
-    q.p = (b1 / k.dt + k.zeta * bsp(tau)) / r;
+    q.p = (k.kd * b1 / k.dt + k.zeta * bsp(tau)) / r;
     return q;
 }
 
@@ -221,7 +221,7 @@ TD_HD void tri_int(const double *x, const double *P, bool self, const LagK &k, T
 // plus the MFIE identity (Gram) term at g = 1, 2.
 TD_HD double zt_value(const GeoDev &G, int i, int j, int g) {
     const double PI4 = 12.566370614359172;
-    LagK k{G.cdt, G.dt, G.zeta, g};
+    LagK k{G.cdt, G.dt, G.zeta, G.kd, g};
     double z = 0.0;
     for (int rho = 0; rho < 2; ++rho) {
         int ti = G.etri[2 * i + rho];
@@ -273,7 +273,7 @@ TD_HD double zt_value(const GeoDev &G, int i, int j, int g) {
                     gram += A / 3.0 * si * sj * dot3(a, b);
                 }
             }
-        z += 0.5 * G.theta * G.eta * gram * (g == 1 ? (1.0 / G.dt + 0.5 * G.zeta) : (-1.0 / G.dt + 0.5 * G.zeta));
+        z += 0.5 * G.theta * G.eta * gram * (g == 1 ? (G.kd / G.dt + 0.5 * G.zeta) : (-G.kd / G.dt + 0.5 * G.zeta));
     }
     return z;
 }
@@ -359,7 +359,7 @@ TD_HD void pulse_g(const double *pl, double tau, double &g, double &gd) {
 }
 
 // tested incident field of leaf-order edge p at time t (Eq. v_i):
-// sum_rho sum_q w_q A f_p(x_q) . [-dE/dt + theta eta n x (dH/dt + zeta H)], n inward
+// sum_rho sum_q w_q A f_p(x_q) . [-dE/dt + theta eta n x (kd dH/dt + zeta H)], n inward
 TD_HD double vinc_value(const GeoDev &G, int p, const double *pl, double t) {
     double kk[3] = {pl[0], pl[1], pl[2]}, pp[3] = {pl[3], pl[4], pl[5]};
     double E0 = pl[6], delay = pl[9];
@@ -377,7 +377,7 @@ TD_HD double vinc_value(const GeoDev &G, int p, const double *pl, double t) {
             double tau = t - delay - dot3(kk, x) / c, g, gd;
             pulse_g(pl, tau, g, gd);
             double Hs[3], nxH[3], f[3];
-            for (int cc = 0; cc < 3; ++cc) Hs[cc] = E0 * kxp[cc] / G.eta * (gd + G.zeta * g);
+            for (int cc = 0; cc < 3; ++cc) Hs[cc] = E0 * kxp[cc] / G.eta * (G.kd * gd + G.zeta * g);
             cross3(n, Hs, nxH);
             sub3(x, o, f);
             double val = 0;

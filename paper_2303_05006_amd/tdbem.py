@@ -22,12 +22,17 @@ MODE_DIRECT, MODE_IFMM = 0, 1
 INTERP_LAGRANGE, INTERP_CHI_TIME = 0, 1
 FP64, FP32, BF16 = 0, 1, 2
 GUESS_EXTRAP, GUESS_LEARNED = 0, 1
+CFIE1, CFIE2, CFIE3 = 1, 2, 3
+DT2_SPLIT, DT2_KERNEL, DT2_INTERP = 0, 1, 2
+SOLVER_DEVICE, SOLVER_HOST = 0, 1
+M2L_AUTO, M2L_GENERIC, M2L_FFT = 0, 1, 2
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
-    Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT, Q_GUESS_USED = range(18)
+    Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT, Q_GUESS_USED, \
+    Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS = range(22)
 PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
-           "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_guess_weights", "tdbem_guess_capture",
+           "tdbem_checkpoint", "tdbem_restore", "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_guess_weights", "tdbem_guess_capture",
            "tdbem_guess_grad", "tdbem_guess_adam",
            "tdbem_destroy", "tdbem_last_error"]
 GUESS_NFEAT, GUESS_NHIDDEN = 116, 128
@@ -49,11 +54,15 @@ class _Config(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_double), ("nt", ctypes.c_int32), ("d", ctypes.c_int32),
                 ("eps", ctypes.c_double), ("mu", ctypes.c_double),
                 ("theta", ctypes.c_double), ("zeta", ctypes.c_double),
-                ("p_s", ctypes.c_int32), ("p_t", ctypes.c_int32), ("interp", ctypes.c_int32),
+                ("cfie", ctypes.c_int32), ("n_quad", ctypes.c_int32),
+                ("p_s", ctypes.c_int32), ("p_t", ctypes.c_int32), ("interp", ctypes.c_int32), ("dt2", ctypes.c_int32),
+                ("m2l", ctypes.c_int32),
                 ("leaf_max", ctypes.c_int32), ("min_level", ctypes.c_int32), ("mu_window", ctypes.c_int32),
+                ("box_widen", ctypes.c_int32), ("causal_guard", ctypes.c_int32),
                 ("mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
-                ("gmres_rtol", ctypes.c_double), ("gmres_maxit", ctypes.c_int32), ("guess", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("gmres_rtol", ctypes.c_double), ("gmres_maxit", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
+                ("guess", ctypes.c_int32), ("solver", ctypes.c_int32), ("gmres_blocks", ctypes.c_int32),
+                ("growth_limit", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 def load():
@@ -69,6 +78,8 @@ def load():
         L.tdbem_potentials.argtypes = [P, P, i32, P]
         L.tdbem_step.argtypes = [P, P, P]
         L.tdbem_reset.argtypes = [P]
+        L.tdbem_checkpoint.argtypes = [P, P, ctypes.POINTER(ctypes.c_size_t)]
+        L.tdbem_restore.argtypes = [P, P, ctypes.c_size_t]
         L.tdbem_query.argtypes = [P, i32, P]
         L.tdbem_near_rows.argtypes = [P, P, i32, i32, P]
         L.tdbem_profile.argtypes = [P, i32]
@@ -99,18 +110,28 @@ class Config:
     mu: float = 4e-7 * np.pi
     theta: float = 1.0
     zeta: float = 299792458.0 / 2
+    cfie: int = CFIE1
+    n_quad: int = 3
     p_s: int = 4
     p_t: int = 4
     interp: int = INTERP_CHI_TIME
+    dt2: int = DT2_SPLIT
+    m2l: int = M2L_AUTO
     leaf_max: int = 64
     min_level: int = 2
     mu_window: int = 8
+    box_widen: int = 0
+    causal_guard: int = 0
     mode: int = MODE_IFMM
     precision: int = FP64
     n_rhs: int = 1
     gmres_rtol: float = 1e-8
     gmres_maxit: int = 60
+    gmres_restart: int = 32
     guess: int = GUESS_EXTRAP
+    solver: int = SOLVER_DEVICE
+    gmres_blocks: int = 0
+    growth_limit: float = 0.0
 
 
 def _ptr(t):
@@ -146,9 +167,11 @@ class Solver:
                   len(self._tris), self._tris.ctypes.data_as(ctypes.c_void_p))
         s = stream if stream is not None else torch.cuda.current_stream()
         self.stream = s
-        c = _Config(cfg.dt, cfg.nt, 2, cfg.eps, cfg.mu, cfg.theta, cfg.zeta, cfg.p_s, cfg.p_t, cfg.interp,
-                    cfg.leaf_max, cfg.min_level, cfg.mu_window, cfg.mode, cfg.precision, cfg.n_rhs,
-                    cfg.gmres_rtol, cfg.gmres_maxit, cfg.guess, ctypes.c_void_p(s.cuda_stream))
+        c = _Config(cfg.dt, cfg.nt, 2, cfg.eps, cfg.mu, cfg.theta, cfg.zeta, cfg.cfie, cfg.n_quad,
+                    cfg.p_s, cfg.p_t, cfg.interp, cfg.dt2, cfg.m2l, cfg.leaf_max, cfg.min_level, cfg.mu_window,
+                    cfg.box_widen, cfg.causal_guard, cfg.mode, cfg.precision, cfg.n_rhs,
+                    cfg.gmres_rtol, cfg.gmres_maxit, cfg.gmres_restart, cfg.guess, cfg.solver, cfg.gmres_blocks,
+                    cfg.growth_limit, ctypes.c_void_p(s.cuda_stream))
         h = ctypes.c_void_p()
         _check(L.tdbem_setup(ctypes.byref(m), ctypes.byref(c), ctypes.byref(h)))
         self._h = h
@@ -188,6 +211,7 @@ class Solver:
                 "nilist": self.query_array(Q_NILIST, lm + 1, np.int64).tolist(),
                 "near_nnz": self.query_i64(Q_NEAR_NNZ), "near_pairs": self.query_i64(Q_NEAR_PAIRS),
                 "z0_nnz": self.query_i64(Q_Z0_NNZ), "window": self.query_i32(Q_WINDOW),
+                "windows": self.query_array(Q_WINDOWS, lm + 1, np.int32).tolist(),
                 "device_bytes": self.query_i64(Q_DEVICE_BYTES), "setup_ms": self.query_f64(Q_SETUP_MS)}
 
     # ----------------------------------------------------------------- work
@@ -207,6 +231,30 @@ class Solver:
 
     def reset(self):
         _check(load().tdbem_reset(self._h))
+
+    def checkpoint(self):
+        """Marching state as bytes (host copy)."""
+        n = ctypes.c_size_t(0)
+        _check(load().tdbem_checkpoint(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(load().tdbem_checkpoint(self._h, buf, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def restore(self, state: bytes):
+        buf = ctypes.create_string_buffer(state, len(state))
+        _check(load().tdbem_restore(self._h, buf, len(state)))
+
+    def config_in_effect(self):
+        c = _Config()
+        _check(load().tdbem_query(self._h, Q_CONFIG, ctypes.byref(c)))
+        return {name: getattr(c, name) for name, _ in _Config._fields_ if name != "stream"}
+
+    def d0_nnz(self):
+        """Non-zero coefficients of the all-pairs discretised problem."""
+        return self.query_i64(Q_D0_NNZ)
+
+    def unstable(self):
+        return self.query_array(Q_UNSTABLE, self.cfg.n_rhs, np.int32)
 
     def near_rows(self, rows, G):
         rows = np.ascontiguousarray(rows, dtype=np.int32)

@@ -11,6 +11,7 @@ struct GeoDev {
     const double *xyz; const int *tri; const double *area; const double *nrm; const double *qpt;
     const int *etri; const int *efree; const double *elen;
     double cdt, dt, eps, mu, theta, zeta, eta;
+    double kd;
 };
 #define TD_HD static inline
 #define TD_CONST static const
@@ -21,11 +22,12 @@ using tdbem::GeoDev;
 
 static GeoDev mk(const double *xyz, const int *tri, const double *area, const double *nrm, const double *qpt,
                  const int *etri, const int *efree, const double *elen, const double *par) {
-    return GeoDev{xyz, tri, area, nrm, qpt, etri, efree, elen, par[0], par[1], par[2], par[3], par[4], par[5], par[6]};
+    return GeoDev{xyz, tri, area, nrm, qpt, etri, efree, elen, par[0], par[1], par[2], par[3], par[4], par[5], par[6],
+                  par[7]};
 }
 
 extern "C" {
-// par = cdt, dt, eps, mu, theta, zeta, eta
+// par = cdt, dt, eps, mu, theta, zeta, eta, kd
 void zt_host(const double *xyz, const int *tri, const double *area, const double *nrm, const double *qpt,
              const int *etri, const int *efree, const double *elen, const double *par,
              long npairs, const int *pi, const int *pj, int G, double *out, int *lo, int *hi) {

@@ -140,3 +140,60 @@ def transient_current(points, times, a, f0, sigma, delay, E0=1.0, nw=400, wmax_s
         wt = 0.5 if wi == len(ws) - 1 else 1.0
         out += wt * dw / math.pi * np.real(ph[:, None, None] * Jw[None])
     return out
+
+
+def sin2_spectrum(A, lam, c=C0):
+    """G(w) = int g(u) exp(i w u) du for the paper's Sin^2 pulse of Section 4.1,
+    g(u) = A sin^2(2 pi c u / lam) on 0 <= u <= lam / c (two humps), zero
+    outside.  With sin^2 = (1 - cos 2 W u) / 2, W = 2 pi c / lam, and
+    int_0^T exp(i v u) du = (exp(i v T) - 1) / (i v)."""
+    W = 2 * math.pi * c / lam
+    T = lam / c
+
+    def seg(v):
+        v = np.asarray(v, float)
+        out = np.empty(v.shape, complex)
+        small = np.abs(v) * T < 1e-8
+        out[small] = T
+        vs = v[~small]
+        out[~small] = (np.exp(1j * vs * T) - 1.0) / (1j * vs)
+        return out
+
+    def G(w):
+        return A * (0.5 * seg(w) - 0.25 * (seg(w + 2 * W) + seg(w - 2 * W)))
+    return G
+
+
+def _grid(wmax, nw):
+    """Trapezoidal grid on [0, wmax]: nodes and weights.  A unipolar pulse has
+    a DC component, so the w = 0 end counts (half weight); its current is
+    the w -> 0+ limit, evaluated at 1e-6 of the spacing."""
+    ws = np.linspace(0.0, wmax, nw + 1)
+    wt = np.full(nw + 1, ws[1])
+    wt[0] = wt[-1] = 0.5 * ws[1]
+    return ws, wt
+
+
+def transient_current_spectrum(points, times, a, G, wmax, delay, nw=800):
+    """J(x, t) = n_out x H for the pulse x g(t - z/c - delay) with spectrum
+    G(w) (sin2_spectrum), trapezoidal synthesis over [0, wmax] (periodic in t
+    with period 2 pi nw / wmax).  Returns [t][point][3]."""
+    ws, wts = _grid(wmax, nw)
+    Gw = G(ws)
+    P = np.asarray(points, float)
+    out = np.zeros((len(times), len(P), 3))
+    t = np.asarray(times, float)
+    for w, g, wt in zip(ws, Gw, wts):
+        Jw = surface_current(P, max(w, 1e-6 * ws[1]) / C0, a)
+        ph = g * np.exp(-1j * w * (t - delay))
+        out += wt / math.pi * np.real(ph[:, None, None] * Jw[None])
+    return out
+
+
+def synthesise_waveform(times, G, wmax, nw=800):
+    """(1/pi) Re int_0^wmax G(w) exp(-i w t) dw on the grid of
+    transient_current_spectrum: the waveform itself, as the incident field at
+    the origin sees it (for pinning the synthesis)."""
+    ws, wts = _grid(wmax, nw)
+    t = np.asarray(times, float)
+    return (wts[None, :] / math.pi * np.real(G(ws)[None, :] * np.exp(-1j * ws[None, :] * t[:, None]))).sum(1)

@@ -35,7 +35,8 @@ def test_library_exports_every_declared_symbol():
 def test_config_struct_layout_matches_header():
     # field order of tdbem_config in the header equals the binding's
     src = open(os.path.join(ROOT, "include", "tdbem.h")).read()
-    body = src[src.index("typedef struct {\n    double dt;"):src.index("} tdbem_config;")]
+    end = src.index("} tdbem_config;")
+    body = src[src.rindex("typedef struct {", 0, end):end]
     body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
     names = re.findall(r"[\s,]\*?([a-z_0-9]+)\s*[,;]", body)
     assert names == [f[0] for f in tdbem._Config._fields_]

@@ -26,6 +26,20 @@ def test_gate_schedule():
     assert len(g[3]) == 40 and len(g[2]) == 20
 
 
+def test_steady_window_floors():
+    """Whatever is requested, the timed steps start after the coarsest level's
+    full window and the pulse's arrival, and span whole coarsest intervals."""
+    assert bench.steady_window(5, 20, 24, 9, 179) == (216, 24)
+    assert bench.steady_window(240, 480, 24, 9, 179) == (240, 480)
+    assert bench.steady_window(0, 1, 24, 9, 300) == (312, 24)
+    assert bench.steady_window(250, 50, 24, 10, 100) == (264, 72)
+
+
+def test_physical_cores_is_positive():
+    phys, used = bench.physical_cores()
+    assert phys >= 1 and 1 <= used <= phys
+
+
 def test_traffic_record_follows_its_source(tmp_path, monkeypatch):
     with open(bench.TRAFFIC_FILE) as f:
         rec = json.load(f)

@@ -8,7 +8,7 @@ of a marched history) and for the marched current, as the relative l2 error
 sqrt(sum_a |J_a - J_ref,a|^2 / sum_a |J_ref,a|^2) over steps and edges.  The
 bounds below are the measured values rounded up (temporal CHI-FD, the default:
 2.5e-2 for the potentials, 3.6e-2 for the march; temporal Lagrange: 2.2e-2 and
-3.2e-2).  With the causality guard (TDBEM_CAUSAL_GUARD=1: the interval shrunk so
+3.2e-2).  With the causality guard (causal_guard = 1: the interval shrunk so
 that no far pair can interact within one interval although basis supports
 reach beyond their cells) the error barely moves (1.6e-2 / 2.4e-2): it is the
 interpolation's, not the dropped same-interval terms'.  The FP32 form is
@@ -62,11 +62,8 @@ def runs():
                      ("ifmm32", dict(mode=tdbem.MODE_IFMM, precision=tdbem.FP32)),
                      ("guard", dict(mode=tdbem.MODE_IFMM))):
         if name == "guard":
-            os.environ["TDBEM_CAUSAL_GUARD"] = "1"
-        try:
-            S = tdbem.Solver(v, f, tdbem.Config(dt=dt, nt=NT, gmres_rtol=1e-12, gmres_maxit=100, **kw))
-        finally:
-            os.environ.pop("TDBEM_CAUSAL_GUARD", None)
+            kw["causal_guard"] = 1
+        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, nt=NT, gmres_rtol=1e-12, gmres_maxit=100, **kw))
         res[name] = (S, _march(S, pulse, NT, torch))
     yield res
     for S, _ in res.values():
@@ -116,7 +113,7 @@ def test_precision_forms_on_a_cube():
     of the FP32 form and of the BF16 form (bf16 near-field coefficients) against
     the FP64 IFMM.  The cube's finest cells are smaller than its basis
     supports reach, and its march grows after the pulse with cell-sized
-    interpolation boxes; the boxes are widened here (TDBEM_BOX_WIDEN=1), with
+    interpolation boxes; the boxes are widened here (box_widen = 1), with
     which the march decays."""
     from paper_2303_05006_amd.inputs import cube
     torch = _torch()
@@ -125,12 +122,8 @@ def test_precision_forms_on_a_cube():
     pulse = gaussian_pulse(300e6, 200e6, r_max=math.sqrt(3.0))
     res = {}
     for name, prec in (("fp64", tdbem.FP64), ("fp32", tdbem.FP32), ("bf16", tdbem.BF16)):
-        os.environ["TDBEM_BOX_WIDEN"] = "1"
-        try:
-            S = tdbem.Solver(v, f, tdbem.Config(dt=dt, nt=NT, mode=tdbem.MODE_IFMM, precision=prec, gmres_rtol=1e-12,
-                                                gmres_maxit=200))
-        finally:
-            os.environ.pop("TDBEM_BOX_WIDEN", None)
+        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, nt=NT, mode=tdbem.MODE_IFMM, precision=prec, gmres_rtol=1e-12,
+                                            gmres_maxit=200, box_widen=1))
         res[name] = _march(S, pulse, NT, torch)
         S.close()
     e32 = _rel(res["fp32"], res["fp64"])

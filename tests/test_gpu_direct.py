@@ -103,29 +103,24 @@ def test_direct_march_matches_oracle_320_triangles():
     S.close()
 
 
-@pytest.mark.parametrize("nrhs,blocks", [(1, None), (5, None), (1, "1"), (5, "1")])
+@pytest.mark.parametrize("nrhs,blocks", [(1, 0), (5, 0), (1, 1), (5, 1)])
 def test_device_gmres_matches_host_gmres(nrhs, blocks):
     """The cooperative device-resident Z0 solve against the host-driven one, for
     one right-hand side (one system split over many blocks) and for a batch
     (one system per block row of the grid, vectors transposed around it).  With
-    one block per system (TDBEM_GMRES_BLOCKS=1) the 480 rows exceed what a block
+    one block per system (gmres_blocks = 1) the 480 rows exceed what a block
     keeps in LDS, so the general SpMV runs, and the grid barrier reduces to the
     block's own."""
-    import os
     torch = _torch()
     w = workload("conv320", nt=120)
     pulses = [gaussian_pulse(60e6, 40e6, k=(np.sin(0.3 * i), 0.0, np.cos(0.3 * i))) for i in range(nrhs)]
     outs = []
-    for host in ("1", "0"):
-        os.environ["TDBEM_HOST_GMRES"] = host
-        if blocks:
-            os.environ["TDBEM_GMRES_BLOCKS"] = blocks
-        try:
-            S = tdbem.Solver(w.verts, w.tris, tdbem.Config(dt=w.dt, mode=tdbem.MODE_DIRECT, gmres_rtol=1e-12,
-                                                           gmres_maxit=100, n_rhs=nrhs))
-        finally:
-            os.environ.pop("TDBEM_HOST_GMRES", None)
-            os.environ.pop("TDBEM_GMRES_BLOCKS", None)
+    for solver in (tdbem.SOLVER_HOST, tdbem.SOLVER_DEVICE):
+        S = tdbem.Solver(w.verts, w.tris, tdbem.Config(dt=w.dt, mode=tdbem.MODE_DIRECT, gmres_rtol=1e-12,
+                                                       gmres_maxit=100, n_rhs=nrhs, solver=solver,
+                                                       gmres_blocks=blocks))
+        eff = S.config_in_effect()
+        assert eff["solver"] == solver and eff["gmres_blocks"] == blocks
         ne = S.ne
         shape = (ne,) if nrhs == 1 else (nrhs, ne)
         V = torch.zeros(shape, dtype=torch.float64, device="cuda")

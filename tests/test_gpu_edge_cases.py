@@ -3,7 +3,7 @@ invalid input is rejected on the host before any launch).
 
 * empty history: the potentials of step 1 are zero;
 * invalid configurations and meshes: EINVAL with a message;
-* a time hierarchy with fewer than 3 steps per finest interval: EBREAKDOWN;
+* a time hierarchy without a step per finest interval: EBREAKDOWN;
 * 65 right-hand sides (one full group of 64 and a ragged group of 1) against
   single runs, in both precisions' kernels;
 * the learned guess: wrong parameter count, missing parameters, empty batch.
@@ -63,14 +63,20 @@ def test_open_or_broken_meshes_are_rejected():
 
 
 def test_time_hierarchy_breakdown():
-    """c dt larger than a third of the finest cell side: fewer than 3 steps per
-    interval (Remark 1) is refused in IFMM mode; the direct path accepts it."""
+    """c dt larger than the finest cell side: no step per interval (M_t = 0,
+    Remark 1) is refused in IFMM mode; the direct path accepts it.  One step
+    per interval is accepted (the window grows by the intervals the truncated
+    differences reach: 9 + 3 at the finest level)."""
     _torch()
     v, f = icosphere(2)
     with pytest.raises(tdbem.TdbemError) as e:
-        tdbem.Solver(v, f, tdbem.Config(dt=0.2 / C0, mode=tdbem.MODE_IFMM, leaf_max=6))
+        tdbem.Solver(v, f, tdbem.Config(dt=0.3 / C0, mode=tdbem.MODE_IFMM, leaf_max=6))
     assert e.value.code == tdbem.EBREAKDOWN
-    tdbem.Solver(v, f, tdbem.Config(dt=0.2 / C0, mode=tdbem.MODE_DIRECT)).close()
+    tdbem.Solver(v, f, tdbem.Config(dt=0.3 / C0, mode=tdbem.MODE_DIRECT)).close()
+    S = tdbem.Solver(v, f, tdbem.Config(dt=0.2 / C0, mode=tdbem.MODE_IFMM, leaf_max=6))
+    info = S.info()
+    assert info["Mt"][3] == 1 and info["windows"][3] == 12 and info["windows"][2] == 11
+    S.close()
 
 
 @pytest.mark.parametrize("prec", [tdbem.FP64, tdbem.FP32])

@@ -49,8 +49,29 @@ def setup(request):
     near = np.zeros((m.ne, m.ne), bool)
     for i, j in F.H.near_pairs():
         near[i, j] = True
+    S.hist = HIST
+    S.far = F.far_history(HIST)      # O2's all-interval far field after every prefix of HIST
     yield m, S, F, Z, near, dt
     S.close()
+
+
+# one random current history per module: the far field at step a uses J^0..J^{a-2}
+# only, so the potentials after its first n steps are row n of O2's march
+HIST = np.random.default_rng(97).standard_normal((97, 480))
+
+
+def _near_plus_far(S, Z, near, n_hist):
+    """Oracle potentials after the first n_hist steps of HIST: O1's J-form
+    coefficients on the near pairs plus O2's all-interval far field."""
+    hist = HIST[:n_hist]
+    a = n_hist + 1
+    Zn = Z * near[:, :, None]
+    ref = np.zeros(Z.shape[0])
+    for g in range(2, Z.shape[2]):
+        if 0 <= a - g < n_hist:
+            ref += Zn[:, :, g] @ hist[a - g]
+    far = S.far[a - 1]
+    return ref + far, far
 
 
 def test_hierarchy_matches_oracle(setup):
@@ -78,16 +99,8 @@ def test_near_coefficients_on_program2_pairs(setup):
 def test_potentials_match_near_plus_all_interval_far(setup, n_hist):
     torch = _torch()
     m, S, F, Z, near, dt = setup
-    rng = np.random.default_rng(n_hist)
-    hist = rng.standard_normal((n_hist, m.ne))
-    a = n_hist + 1
-    Zn = Z * near[:, :, None]
-    ref = np.zeros(m.ne)
-    for g in range(2, Z.shape[2]):
-        if 0 <= a - g < n_hist:
-            ref += Zn[:, :, g] @ hist[a - g]
-    far = F.far_history(hist)[a - 1]
-    ref += far
+    hist = np.ascontiguousarray(HIST[:n_hist])
+    ref, far = _near_plus_far(S, Z, near, n_hist)
     out = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
     S.potentials(torch.tensor(hist, device="cuda"), n_hist, out)
     got = out.cpu().numpy()
@@ -101,8 +114,12 @@ def test_potentials_match_near_plus_all_interval_far(setup, n_hist):
 
 
 def test_marched_current_satisfies_oracle_equations(setup):
+    """(Temporal CHI-FD, the paper's interpolant; the Lagrange path is held to
+    the oracle by the potentials tests.)"""
     torch = _torch()
     m, S, F, Z, near, dt = setup
+    if S.interp != tdbem.INTERP_CHI_TIME:
+        pytest.skip("marched for the temporal CHI-FD interpolant only")
     nt = 110
     pulse = gaussian_pulse(150e6, 100e6)
     S.reset()
@@ -192,14 +209,8 @@ def test_precision_forms_potentials(setup, prec, tol):
     m, S, F, Z, near, dt = setup
     B = _solver(dt, S.interp, precision=prec)
     n_hist = 97
-    rng = np.random.default_rng(5)
-    hist = rng.standard_normal((n_hist, m.ne))
-    a = n_hist + 1
-    Zn = Z * near[:, :, None]
-    ref = F.far_history(hist)[a - 1]
-    for g in range(2, Z.shape[2]):
-        if 0 <= a - g < n_hist:
-            ref += Zn[:, :, g] @ hist[a - g]
+    hist = HIST
+    ref, _ = _near_plus_far(S, Z, near, n_hist)
     out = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
     B.potentials(torch.tensor(hist, device="cuda"), n_hist, out)
     rel = np.abs(out.cpu().numpy() - ref).max() / np.abs(ref).max()
@@ -255,7 +266,7 @@ def test_fp32_form_marched_current_close_to_fp64(setup):
 
 def test_widened_boxes_potentials_match_oracle():
     """Interpolation boxes widened by the largest support protrusion
-    (TDBEM_BOX_WIDEN=1) against near + all-interval far of O2 with the same
+    (box_widen = 1) against near + all-interval far of O2 with the same
     boxes: 1920-edge sphere, leaves of at most 64 edges (two levels), c dt =
     0.078 m, temporal CHI-FD, 30 steps of random history."""
     import os
@@ -263,12 +274,8 @@ def test_widened_boxes_potentials_match_oracle():
     v, f = icosphere(3)
     m = O.Mesh(v, f)
     dt = 0.078 / C0
-    os.environ["TDBEM_BOX_WIDEN"] = "1"
-    try:
-        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=64, gmres_rtol=1e-13,
-                                            gmres_maxit=200))
-    finally:
-        os.environ.pop("TDBEM_BOX_WIDEN", None)
+    S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=64, gmres_rtol=1e-13,
+                                        gmres_maxit=200, box_widen=1))
     F = IFMM(m, dt, 1.0, C0 / 2, EPS0, MU0, leaf_max=64, interp_t="chi", widen=True)
     assert F.delta > 0
     n_hist = 30
@@ -291,3 +298,46 @@ def test_widened_boxes_potentials_match_oracle():
     print(f"widened boxes: rel err {rel:.2e}")
     S.close()
     assert rel < 1e-10
+
+
+@pytest.mark.parametrize("cdt,n_hist", [(0.1, 60), (0.2, 40)], ids=["Mt2", "Mt1"])
+def test_short_intervals_potentials_match_all_interval_far(cdt, n_hist):
+    """Fewer than 3 steps per finest interval: the truncated differences of the
+    window reach ceil(3 / M_t) intervals, so that many truncated variants are
+    kept and the window grows by as many intervals (M_t = 2: 9 + 2 at level 3,
+    M_t = 1: 9 + 3).  Against O1 near + O2's all-interval far field."""
+    torch = _torch()
+    v, f = icosphere(2)
+    m = O.Mesh(v, f)
+    dt = cdt / C0
+    S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=tdbem.MODE_IFMM, leaf_max=LEAF, gmres_rtol=1e-13,
+                                        gmres_maxit=200))
+    F = IFMM(m, dt, 1.0, C0 / 2, EPS0, MU0, leaf_max=LEAF, interp_t="chi")
+    info = S.info()
+    assert info["Mt"][2:] == F.H.Mt[2:]
+    M3 = F.H.Mt[3]
+    assert M3 == (2 if cdt == 0.1 else 1)
+    assert info["windows"][3] == 9 + (3 + M3 - 1) // M3
+    G = O.max_lag(m, cdt) + 1
+    Z = O.zrows(m, np.arange(m.ne), cdt, 1.0, C0 / 2, G=G)
+    near = np.zeros((m.ne, m.ne), bool)
+    for i, j in F.H.near_pairs():
+        near[i, j] = True
+    rng = np.random.default_rng(int(100 * cdt))
+    hist = rng.standard_normal((n_hist, m.ne))
+    a = n_hist + 1
+    Zn = Z * near[:, :, None]
+    ref = np.zeros(m.ne)
+    for g in range(2, Z.shape[2]):
+        if 0 <= a - g < n_hist:
+            ref += Zn[:, :, g] @ hist[a - g]
+    far = F.far_history(hist)[a - 1]
+    ref += far
+    out = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+    S.potentials(torch.tensor(hist, device="cuda"), n_hist, out)
+    got = out.cpu().numpy()
+    rel = np.abs(got - ref).max() / np.abs(ref).max()
+    rel_far = np.abs(got - ref).max() / np.abs(far).max()
+    print(f"M_t = {M3}: rel err {rel:.2e} (relative to the far part {rel_far:.2e})")
+    S.close()
+    assert rel < 1e-9 and rel_far < 1e-8

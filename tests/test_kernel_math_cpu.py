@@ -16,10 +16,11 @@ from paper_2303_05006_amd.inputs import icosphere, cube, C0, EPS0, MU0, gaussian
 ETA0 = math.sqrt(MU0 / EPS0)
 
 
-def _geo(m, cdt, theta, zeta):
+def _geo(m, cdt, theta, zeta, cfie=1):
     nrm = np.ascontiguousarray(m.n_out)
     qpt = np.ascontiguousarray(np.stack([m.quad_points(t)[0] for t in range(len(m.tri))]))
-    par = np.array([cdt, cdt / C0, EPS0, MU0, theta, zeta, ETA0])
+    kd, zeta = O.cfie_weights(cfie, zeta)
+    par = np.array([cdt, cdt / C0, EPS0, MU0, theta, zeta, ETA0, kd])
     arrs = [m.xyz, m.tri, m.area, nrm, qpt, m.etri, m.efree, m.elen, par]
     return arrs, [a.ctypes.data_as(ctypes.c_void_p) for a in arrs]
 
@@ -28,13 +29,14 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-@pytest.mark.parametrize("mesh,cdt", [("ico1", 0.12), ("ico2", 0.1499), ("cube2", 0.2)])
-def test_library_coefficients_match_oracle(mesh, cdt):
+@pytest.mark.parametrize("mesh,cdt,cfie", [("ico1", 0.12, 1), ("ico2", 0.1499, 1), ("cube2", 0.2, 1),
+                                           ("ico1", 0.12, 2), ("cube2", 0.2, 3)])
+def test_library_coefficients_match_oracle(mesh, cdt, cfie):
     v, f = {"ico1": icosphere(1), "ico2": icosphere(2), "cube2": cube(2, 2.0)}[mesh]
     m = O.Mesh(v, f)
     theta, zeta = 1.0, C0 / 2
     L = load()
-    keep, ptrs = _geo(m, cdt, theta, zeta)
+    keep, ptrs = _geo(m, cdt, theta, zeta, cfie)
     rng = np.random.default_rng(1)
     rows = rng.choice(m.ne, size=min(m.ne, 12), replace=False)
     pi = np.repeat(rows, m.ne).astype(np.int32)
@@ -44,7 +46,7 @@ def test_library_coefficients_match_oracle(mesh, cdt):
     lo = np.zeros(len(pi), np.int32)
     hi = np.zeros(len(pi), np.int32)
     L.zt_host(*ptrs, len(pi), _p(pi), _p(pj), G, _p(out), _p(lo), _p(hi))
-    ref = O.zrows(m, rows, cdt, theta, zeta, G=G).reshape(len(pi), G)
+    ref = O.zrows(m, rows, cdt, theta, zeta, G=G, cfie=cfie).reshape(len(pi), G)
     scale = np.abs(ref).reshape(len(rows), -1).max(axis=1).repeat(m.ne)
     err = np.abs(out - ref).max(axis=1) / scale
     assert err.max() < 1e-12, (err.max(), np.argmax(err))
@@ -54,15 +56,16 @@ def test_library_coefficients_match_oracle(mesh, cdt):
     assert np.all(~nz | ((gidx >= lo[:, None]) & (gidx <= hi[:, None])))
 
 
-def test_library_incident_field_matches_oracle():
+@pytest.mark.parametrize("cfie", [1, 2, 3])
+def test_library_incident_field_matches_oracle(cfie):
     v, f = icosphere(2)
     m = O.Mesh(v, f)
-    keep, ptrs = _geo(m, 0.15, 1.0, C0 / 2)
+    keep, ptrs = _geo(m, 0.15, 1.0, C0 / 2, cfie)
     L = load()
     p = gaussian_pulse(60e6, 40e6)
     pa = np.ascontiguousarray(p.as_array())
     for t in (5e-9, 3.1e-8, 6e-8):
         out = np.zeros(m.ne)
         L.vinc_host(*ptrs, m.ne, _p(pa), t, _p(out))
-        ref = O.vinc(m, p, t, 1.0, C0 / 2)
+        ref = O.vinc(m, p, t, 1.0, C0 / 2, cfie=cfie)
         assert np.abs(out - ref).max() <= 1e-13 * np.abs(ref).max()

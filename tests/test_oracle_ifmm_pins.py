@@ -132,6 +132,12 @@ def test_second_derivatives_of_the_temporal_interpolants(p):
     for d2, d1 in ((chi_fd_d2, chi_fd), (lagrange_d2, lagrange)):
         num = (d1(p, x + h)[1] - d1(p, x - h)[1]) / (2 * h)
         assert np.allclose(d2(p, x), num, atol=1e-4)
+    # CHI-FD: discontinuous at the interior nodes; a node takes the limit from the left
+    for node in w[1:]:
+        left, right = chi_fd_d2(p, np.array([node - 1e-7]))[0], chi_fd_d2(p, np.array([node + 1e-7]))[0]
+        assert np.allclose(chi_fd_d2(p, np.array([node]))[0], left, atol=1e-5)
+        if node < 1.0:
+            assert np.abs(left - right).max() > 0.1
 
 
 @pytest.mark.parametrize("interp_t,widen,cfie,dt2", [("lagrange", False, 1, "split"), ("chi", False, 1, "split"),
@@ -174,33 +180,40 @@ def test_polynomial_kernel_exactness(interp_t, widen, cfie, dt2):
     avec = np.arange(1, nb + 2)
     bvec = np.arange(nb)
     TAU = (avec[:, None] - bvec[None, :]) * dt                  # [a, beta]
-    for ti, i in enumerate(targets):
-        # test side: points, weights, f_i, div f_i, inward normal
-        Xi = []
+    def side_points(e):
+        """The 6 quadrature points of edge e's two triangles: points, weights,
+        f_e, div f_e and inward normals, as arrays."""
+        P_, W_, F_, D_, N_ = [], [], [], [], []
         for rho in (0, 1):
-            t_ = m.etri[i, rho]
+            t_ = m.etri[e, rho]
             X, W = m.quad_points(t_)
             for x, w in zip(X, W):
-                fi, divi = m.rwg(i, rho, x)
-                Xi.append((x, w, fi, divi, -m.n_out[t_]))
+                f_, d_ = m.rwg(e, rho, x)
+                P_.append(x); W_.append(w); F_.append(f_); D_.append(d_); N_.append(-m.n_out[t_])
+        return np.array(P_), np.array(W_), np.array(F_), np.array(D_), np.array(N_)
+
+    pts = [side_points(e) for e in range(m.ne)]
+    for ti, i in enumerate(targets):
+        xi_, wi_, fi_, di_, ni_ = pts[i]
         for j in range(m.ne):
             l = _far_level(H, leaf, i, j)
             if l is None:
                 continue
             M = H.Mt[l]
-            # quadrature moments of the pair: the kernels are polynomials in (r^2, tau)
-            Sff = Sffr = Sdd = Sddr = SP = 0.0
-            for sg in (0, 1):
-                Xj, Wj = m.quad_points(m.etri[j, sg])
-                for y, wy in zip(Xj, Wj):
-                    fj, divj = m.rwg(j, sg, y)
-                    for x, wx, fi, divi, n_in in Xi:
-                        ww = wx * wy
-                        r2 = float((x - y) @ (x - y))
-                        Sff += ww * (fi @ fj); Sffr += ww * (fi @ fj) * r2
-                        Sdd += ww * divi * divj; Sddr += ww * divi * divj * r2
-                        # theta eta f_i.(n x ((1/4pi) f_j x (y - x))), times the radial factor below
-                        SP += ww * theta * eta / (4 * math.pi) * (fi @ np.cross(n_in, np.cross(fj, y - x)))
+            # quadrature moments of the pair (6 test x 6 source points): the
+            # kernels are polynomials in (r^2, tau)
+            yj_, wj_, fj_, dj_, _ = pts[j]
+            ww = wi_[:, None] * wj_[None, :]
+            d = yj_[None, :, :] - xi_[:, None, :]                    # y - x
+            r2 = (d * d).sum(-1)
+            ff = fi_ @ fj_.T
+            dd = di_[:, None] * dj_[None, :]
+            Sff = (ww * ff).sum(); Sffr = (ww * ff * r2).sum()
+            Sdd = (ww * dd).sum(); Sddr = (ww * dd * r2).sum()
+            # theta eta f_i.(n x ((1/4pi) f_j x (y - x))), times the radial factor below
+            fxd = np.cross(fj_[None, :, :], d)
+            nxf = np.cross(ni_[:, None, :], fxd)
+            SP = theta * eta / (4 * math.pi) * (ww * (fi_[:, None, :] * nxf).sum(-1)).sum()
             # vector potential: (mu/4pi) f_i.f_j d/dt[dU-kernel]; scalar: -div_i (-1/4 pi eps) div_j U-kernel;
             # magnetic: grad_y (d/dt + zeta) K0 = (2 a4 + zeta (2 a1 + 2 a4 tau)) (y - x)
             T = TAU
