@@ -188,6 +188,20 @@ int tdbem_potentials(tdbem_ctx *ctx, const double *hist_dev, int32_t n_hist, dou
  * misses the tolerance (the iterate is still returned). */
 int tdbem_step(tdbem_ctx *ctx, const double *V_dev, double *J_dev);
 
+/* For callers that cannot allocate device memory during the march (code under
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * step as tdbem_step, with the Z0 solve's workspace (Krylov vectors, partial
+ * sums, status and grid-barrier words) taken from a static 16 MiB array of the
+ * library instead of the context; nothing is allocated by the call.  Limit:
+ * n_rhs (35 N_e + 16896) + 2 N_e n_rhs [n_rhs > 1] + 1024 n_rhs + 2 n_rhs doubles
+ * <= 2^21 (about N_e n_rhs <= 55000); beyond it TDBEM_EINVAL.  The array is
+ * shared by every context on a device and keeps the last call's contents:
+ * calls that overlap on one device race.  Needs the device solver
+ * (TDBEM_SOLVER_DEVICE); with phase timing on (tdbem_profile) the timing
+ * events are still created on first use.  The size check comes before any
+ * work: a refused call leaves the context unchanged. */
+int tdbem_step_noalloc(tdbem_ctx *ctx, const double *V_dev, double *J_dev);
+
 /* Restart the march at alpha = 1 with zero history. */
 int tdbem_reset(tdbem_ctx *ctx);
 

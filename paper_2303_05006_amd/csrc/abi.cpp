@@ -67,6 +67,10 @@ void launch_gather_vals(const double *val, const int64_t *idx, int64_t n, double
 int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, bool *ok, hipStream_t s);
 size_t gmres_work_doubles(const tdbem_ctx *C, int maxit);
 bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s);
+bool gmres_coop_launch_static(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s,
+                              int **iflag_out);
+double *noalloc_scratch(size_t *capacity);
+size_t noalloc_need(const tdbem_ctx *C);
 size_t gmres_coop_work_doubles(int ne, int nrhs);
 
 // weights of the MFIE's time derivative (kd) and of the MFIE (zeta) in the
@@ -326,6 +330,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_HIP(hipStreamSynchronize(s));
     C->alpha = 1;
     C->fingerprint = fingerprint(C);
+    noalloc_scratch(nullptr);       // the allocation-free step's workspace address on this device
     C->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
@@ -357,7 +362,8 @@ static bool monitor_update(tdbem_ctx *C) {
     return trip;
 }
 
-static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, const double *Jgiven) {
+static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, const double *Jgiven,
+                     bool noalloc = false) {
     hipStream_t s = C->stream;
     const int64_t nv = (int64_t)C->ne * C->nrhs;
     int a = C->alpha;
@@ -381,13 +387,18 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
         {
             PhaseScope ps(C->prof, TDBEM_PH_GMRES, s);
             const int maxit = std::max(1, C->cfg.gmres_maxit);
-            if (C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s)) {
+            int *dflag = C->d_iflag;
+            const bool launched = noalloc
+                ? gmres_coop_launch_static(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s, &dflag)
+                : C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s);
+            TD_REQUIRE(launched || !noalloc, TDBEM_EHIP, "the device cannot run the cooperative solve");
+            if (launched) {
                 const size_t nf = 4 * (size_t)C->nrhs;
                 if (monitor) {
                     launch_colnorm2(C, C->d_x, C->d_stat, 1, s);
                     TD_HIP(hipMemcpyAsync(C->h_stat, C->d_stat, 2 * C->nrhs * sizeof(double), hipMemcpyDeviceToHost, s));
                 }
-                TD_HIP(hipMemcpyAsync(C->h_iflag, C->d_iflag, nf * sizeof(int), hipMemcpyDeviceToHost, s));
+                TD_HIP(hipMemcpyAsync(C->h_iflag, dflag, nf * sizeof(int), hipMemcpyDeviceToHost, s));
                 TD_HIP(hipStreamSynchronize(s));
                 int its = 0;
                 bool timeout = false;
@@ -398,7 +409,7 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
                 }
                 C->last_iters = its;
                 if (timeout) {
-                    TD_HIP(hipMemset(C->d_gbar, 0, (size_t)GMRES_BAR_WORDS * C->nrhs * sizeof(unsigned)));
+                    if (!noalloc) TD_HIP(hipMemset(C->d_gbar, 0, (size_t)GMRES_BAR_WORDS * C->nrhs * sizeof(unsigned)));
                     throw Error{TDBEM_EHIP, "device solve: a grid barrier wait timed out"};
                 }
             } else {
@@ -608,6 +619,24 @@ int tdbem_restore(tdbem_ctx *C, const void *buf, size_t len) {
     if (!C || !buf) { set_error("null argument"); return TDBEM_EINVAL; }
     TD_GUARD({ restore_impl(C, (const char *)buf, len); });
     return TDBEM_OK;
+}
+
+int tdbem_step_noalloc(tdbem_ctx *C, const double *V, double *J) {
+    if (!C || !V || !J) { set_error("null argument"); return TDBEM_EINVAL; }
+    if (!C->use_coop) { set_error("the allocation-free step needs the device solver"); return TDBEM_EINVAL; }
+    int rc = TDBEM_OK;
+    TD_GUARD({
+        size_t cap = 0;
+        noalloc_scratch(&cap);
+        const size_t need = noalloc_need(C);
+        TD_REQUIRE(need <= cap, TDBEM_EINVAL,
+                   "the allocation-free step needs " + std::to_string(need * 8) + " bytes of workspace; the static "
+                   "array holds " + std::to_string(cap * 8) + " (N_e x n_rhs too large)");
+        rc = step_impl(C, V, J, true, nullptr, true);
+    });
+    if (rc == TDBEM_ENOCONV) set_error("GMRES did not reach the tolerance");
+    if (rc == TDBEM_EUNSTABLE) set_error("late-time growth: the current exceeds growth_limit times its norm during the excitation");
+    return rc;
 }
 
 int tdbem_reset(tdbem_ctx *C) {

@@ -12,6 +12,9 @@
 // loop trip counts are bounded by the iteration cap.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+
 #include "tdbem_internal.h"
 
 
@@ -406,7 +409,23 @@ static size_t sys_work(int ne) { return (size_t)(GM_MAXV + 2) * ne + (size_t)2 *
 // not all fit.  The status
 // words of system r are C->d_iflag[4r..4r+2].  Returns false if the device
 // cannot co-schedule the grid (the caller then uses the host-driven solver).
+// fill of 32-bit words (clears barrier words without a memset node)
+__global__ void k_fill_u32(int64_t n, unsigned v, unsigned *p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+bool gmres_coop_launch_ws(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s,
+                          double *work, int *iflag, unsigned *gbar);
+
 bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s) {
+    return gmres_coop_launch_ws(C, b, x, rtol, maxit, s, C->d_work, C->d_iflag, C->d_gbar);
+}
+
+// The same solve with its workspace (Krylov vectors, transposes, partial sums),
+// status words and barrier words given by the caller.
+bool gmres_coop_launch_ws(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s,
+                          double *work_in, int *iflag, unsigned *gbar) {
     int dev = 0;
     TD_HIP(hipGetDevice(&dev));
     int coop = 0;
@@ -430,7 +449,7 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
     if (nbx < 1 || resident < 1) return false;
     const int per_launch = std::max(1, resident / nbx);
     const int m = std::min(GM_MAXV - 1, std::max(1, std::min(maxit, C->cfg.gmres_restart)));
-    double *work = C->d_work;
+    double *work = work_in;
     const double *bs = b;
     double *xs = x;
     if (nr > 1) {                       // systems contiguous: [nrhs][ne]
@@ -453,8 +472,8 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
         A.w0 = A.V + (size_t)(m + 1) * ne;
         A.w1 = A.w0 + ne;
         A.part = A.w1 + ne;
-        A.out = C->d_iflag + 4 * r0;
-        A.bar = C->d_gbar + (size_t)GMRES_BAR_WORDS * r0;
+        A.out = iflag + 4 * r0;
+        A.bar = gbar + (size_t)GMRES_BAR_WORDS * r0;
         void *args[] = {&A};
         TD_HIP(hipLaunchCooperativeKernel((const void *)k_gmres_coop, dim3(nbx, cnt), dim3(GM_THREADS), args, 0, s));
     }
@@ -465,6 +484,60 @@ bool gmres_coop_launch(tdbem_ctx *C, const double *b, double *x, double rtol, in
 
 size_t gmres_coop_work_doubles(int ne, int nrhs) {
     return (size_t)nrhs * sys_work(ne) + (nrhs > 1 ? (size_t)2 * ne * nrhs : 0);
+}
+
+// ---------------------------------------------- allocation-free workspace
+// tdbem_step_noalloc takes the device solve's workspace, status words and
+// barrier words from this file-scope array instead of the context's
+// allocations (every call on a device shares that device's copy, which keeps
+// the last call's contents; overlapping calls on one device race).  In host
+// code the array's name is not a device address: its address is taken per
+// device with hipGetSymbolAddress (the device current at the time) and only
+// that address is used.
+static constexpr size_t NOALLOC_DOUBLES = (size_t)2 << 20;      // 16 MiB
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+static constexpr int NOALLOC_MAX_DEVICES = 64;
+static double *g_scratch[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+double *noalloc_scratch(size_t *capacity) {
+    int dev = 0;
+    TD_HIP(hipGetDevice(&dev));
+    TD_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, TDBEM_EINVAL, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        TD_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch[dev] = (double *)ptr;
+    }
+    if (capacity) *capacity = NOALLOC_DOUBLES;
+    return g_scratch[dev];
+}
+
+// doubles of the static workspace one solve of C needs: barrier words, status
+// words, then the solve's own workspace
+size_t noalloc_need(const tdbem_ctx *C) {
+    const size_t nr = C->nrhs;
+    return (GMRES_BAR_WORDS * nr + 1) / 2 + (4 * nr + 1) / 2 + gmres_coop_work_doubles(C->ne, C->nrhs);
+}
+
+// the solve of one step on the static workspace: barrier words cleared by a
+// fill kernel, then the cooperative launch; status words left in *iflag_out
+bool gmres_coop_launch_static(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit, hipStream_t s,
+                              int **iflag_out) {
+    size_t cap = 0;
+    double *base = noalloc_scratch(&cap);
+    const size_t nr = C->nrhs;
+    const size_t bar_d = (GMRES_BAR_WORDS * nr + 1) / 2, flag_d = (4 * nr + 1) / 2;
+    TD_REQUIRE(noalloc_need(C) <= cap, TDBEM_EINVAL, "the allocation-free step's workspace does not fit");
+    unsigned *gbar = (unsigned *)base;
+    int *iflag = (int *)(base + bar_d);
+    double *work = base + bar_d + flag_d;
+    const int64_t nb = (int64_t)GMRES_BAR_WORDS * nr;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, nb, 0u, gbar);
+    TD_HIP(hipGetLastError());
+    *iflag_out = iflag;
+    return gmres_coop_launch_ws(C, b, x, rtol, maxit, s, work, iflag, gbar);
 }
 
 }  // namespace tdbem

@@ -31,7 +31,8 @@ Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NIL
     Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS = range(22)
 PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
-EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_reset",
+EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_step_noalloc",
+           "tdbem_reset",
            "tdbem_checkpoint", "tdbem_restore", "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_guess_weights", "tdbem_guess_capture",
            "tdbem_guess_grad", "tdbem_guess_adam",
            "tdbem_destroy", "tdbem_last_error"]
@@ -77,6 +78,7 @@ def load():
         L.tdbem_incident_planewave.argtypes = [P, P, i32, P]
         L.tdbem_potentials.argtypes = [P, P, i32, P]
         L.tdbem_step.argtypes = [P, P, P]
+        L.tdbem_step_noalloc.argtypes = [P, P, P]
         L.tdbem_reset.argtypes = [P]
         L.tdbem_checkpoint.argtypes = [P, P, ctypes.POINTER(ctypes.c_size_t)]
         L.tdbem_restore.argtypes = [P, P, ctypes.c_size_t]
@@ -222,6 +224,10 @@ class Solver:
 
     def step(self, V, J):
         _check(load().tdbem_step(self._h, _ptr(V), _ptr(J)))
+
+    def step_noalloc(self, V, J):
+        """tdbem_step with the solve's workspace in the library's static array."""
+        _check(load().tdbem_step_noalloc(self._h, _ptr(V), _ptr(J)))
 
     def step_rc(self, V, J):
         return load().tdbem_step(self._h, _ptr(V), _ptr(J))
