@@ -193,11 +193,13 @@ def make_solver(torch, tdbem, w, form, guess, rtol):
     return S, time.perf_counter() - t0
 
 
-def march(torch, S, V, lead, K, last, traj):
+def march(torch, S, V, lead, K, last, traj, deferred=False):
     """Untimed steps 1..lead, timed steps lead+1..lead+K, untimed steps up to
     last, on the resident incident fields V [last][rhs][N_e]; traj (or None)
-    receives J of every step.  Returns (seconds, GMRES iterations of the timed
-    steps)."""
+    receives J of every step.  deferred: the timed steps in one tdbem_march
+    call (the same kernels; each step's solver status read once at the end)
+    instead of K tdbem_step calls.  Returns (seconds, GMRES iterations of the
+    timed steps, phase times)."""
     J = torch.zeros(V.shape[1:], dtype=torch.float64, device="cuda")
 
     def run(a):
@@ -210,19 +212,34 @@ def march(torch, S, V, lead, K, last, traj):
     torch.cuda.synchronize()
     S.profile(True)
     iters = []
+    out = traj[lead:lead + K] if traj is not None else (
+        torch.zeros((K,) + tuple(V.shape[1:]), dtype=torch.float64, device="cuda") if deferred else None)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for a in range(lead + 1, lead + K + 1):
-        run(a)
-        iters.append(S.gmres_iters())
+    if deferred:
+        rc, st, its = S.march(V[lead:lead + K], out, with_iters=True)
+        if rc != tdbem_codes()["OK"]:
+            raise RuntimeError(f"march returned {rc}")
+        iters.extend(int(x) for x in its)
+    else:
+        for a in range(lead + 1, lead + K + 1):
+            run(a)
+            iters.append(S.gmres_iters())
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
+    if deferred:
+        J.copy_(out[-1])
     ph = S.phase_times()
     S.profile(False)
     for a in range(lead + K + 1, last + 1):
         run(a)
     torch.cuda.synchronize()
     return el, iters, ph
+
+
+def tdbem_codes():
+    from paper_2303_05006_amd import tdbem
+    return {"OK": tdbem.OK}
 
 
 def kernel_rooflines(info, ph, lead, K, nr, prec_fp64, form):
@@ -264,7 +281,7 @@ def rel_l2(a, b):
     return float(((a - b) ** 2).sum().sqrt() / (b ** 2).sum().sqrt())
 
 
-def batched_runs(torch, tdbem, lead, K, rtol, single_fp64_steps_per_s):
+def batched_runs(torch, tdbem, lead, K, rtol, single_fp64_steps_per_s, deferred=True):
     """64 incident fields (Fibonacci directions, seeded polarisations) marched
     together: the plain FP64 form and the chosen form (FP32 near values and
     M2L, learned initial guess), timed over K steady-state steps after the
@@ -284,7 +301,7 @@ def batched_runs(torch, tdbem, lead, K, rtol, single_fp64_steps_per_s):
         for a in range(1, last + 1):
             S.incident(w.pulses, a, V[a - 1])
         traj = torch.zeros((last, nr, S.ne), dtype=torch.float64, device="cuda")
-        el, iters, ph = march(torch, S, V, lead, K, last, traj)
+        el, iters, ph = march(torch, S, V, lead, K, last, traj, deferred=deferred)
         roof, _ = kernel_rooflines(S.info(), ph, lead, K, nr, form == "fp64", form)
         out[key] = {"form": form + (" + learned initial guess" if guess == "learned" else ""),
                     "steps_per_s": K / el, "rhs_steps_per_s": nr * K / el, "ms_per_step": el / K * 1e3,
@@ -299,6 +316,119 @@ def batched_runs(torch, tdbem, lead, K, rtol, single_fp64_steps_per_s):
     out["chosen"]["rhs_throughput_vs_fp64_single"] = out["chosen"]["rhs_steps_per_s"] / single_fp64_steps_per_s
     del trajs
     torch.cuda.empty_cache()
+    return out
+
+
+def far_study(torch, tdbem):
+    """Dense (matrix cores) against Fourier-domain M2L at p = 4, 6, 8: the M2L
+    phase per launch over the potentials of a seeded random history (the far
+    field's gates of every level), with the dense form's algorithmic FLOP and
+    the Fourier form's algorithmic bytes (diagonal products: transformed
+    moments and kernels read once per (target, entry, lag), sums written once)
+    per launch.  Also the relative difference of the two forms' potentials."""
+    from paper_2303_05006_amd.inputs import icosphere, C0
+    out = []
+    for p, level, cdt, n_hist in ((4, 4, 0.02, 120), (6, 4, 0.02, 120), (8, 3, 0.04, 60)):
+        v, f = icosphere(level)
+        rng = np.random.default_rng(p)
+        hist = torch.tensor(rng.standard_normal((n_hist, 3 * len(f) // 2)), device="cuda")
+        pots = {}
+        for name, m2l in (("dense", tdbem.M2L_AUTO), ("fft", tdbem.M2L_FFT)):
+            S = tdbem.Solver(v, f, tdbem.Config(dt=cdt / C0, mode=tdbem.MODE_IFMM, p_s=p, p_t=p, leaf_max=64, m2l=m2l))
+            info = S.info()
+            o = torch.zeros(S.ne, dtype=torch.float64, device="cuda")
+            S.profile(True)
+            t0 = time.perf_counter()
+            S.potentials(hist, n_hist, o)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ph = S.phase_times()
+            S.profile(False)
+            pots[name] = o.clone()
+            nn, nf = p ** 4, (2 * p) ** 3 * (p + 1)
+            work, nl = 0.0, 0
+            for l in range(2, info["lmax"] + 1):
+                M = info["Mt"][l]
+                for a in range(M, n_hist + 1, M):
+                    lags = min(info["windows"][l], a // M)
+                    nl += 1
+                    if name == "dense":
+                        work += info["nilist"][l] * lags * 7 * 2.0 * nn * nn
+                    else:
+                        work += (info["nilist"][l] * lags * (7 + 2) + info["ncells"][l] * 7) * nf * 16.0
+            ms = ph["m2l"][0] / max(ph["m2l"][1], 1)
+            rate = work / max(ph["m2l"][1], 1) / (ms * 1e-3)
+            r = {"p": p, "m2l": name, "triangles": len(f), "c_dt": cdt, "history_steps": n_hist,
+                 "m2l_ms_total": ph["m2l"][0], "launches": ph["m2l"][1], "ms_per_launch": ms,
+                 "potentials_wall_s": wall, "device_gb": info["device_bytes"] / 1e9}
+            if name == "dense":
+                r.update({"flop_per_launch": work / max(nl, 1), "achieved_tflops": rate / 1e12,
+                          "frac_fp64_mfma": rate / PEAK_FP64})
+            else:
+                r.update({"bytes_per_launch": work / max(nl, 1), "achieved_gbs": rate / 1e9,
+                          "frac_hbm": rate / PEAK_HBM})
+            out.append(r)
+            S.close()
+            torch.cuda.empty_cache()
+        d = float((pots["fft"] - pots["dense"]).abs().max() / pots["dense"].abs().max())
+        out[-1]["rel_diff_vs_dense"] = d
+        print(json.dumps(out[-2]), flush=True)
+        print(json.dumps(out[-1]), flush=True)
+    return out
+
+
+def guess_study(torch, tdbem, nt=1000, n_pulses=2):
+    """The learned initial guess on a held-out body: the 20480-triangle
+    ellipsoid (semi-axes 1, 1, 2 m), c dt = 0.02 m, pulses from seeds the
+    training never drew (f0 in [50, 150] MHz), FP64 fast method, one field at a
+    time.  Per guess (quadratic extrapolation, the trained network, and a
+    network with zero weights as the control): GMRES iterations per step over
+    steps 201..nt-1, steps/s over the march, the learned guess's share of steps,
+    and the relative l2 difference of the marched current from the
+    extrapolation run."""
+    from paper_2303_05006_amd.inputs import ellipsoid, random_pulses, C0
+    from paper_2303_05006_amd.train_guess import DEFAULT_OUT
+    v, f = ellipsoid(5)
+    dt = 0.02 / C0
+    pulses = random_pulses(n_pulses, seed=7777, r_max=2.0)
+    trained = np.load(DEFAULT_OUT)
+    out, ref = {}, None
+    for name, guess, params in (("extrapolation", tdbem.GUESS_EXTRAP, None),
+                                ("learned", tdbem.GUESS_LEARNED, trained),
+                                ("zero_weights", tdbem.GUESS_LEARNED, np.zeros_like(trained))):
+        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, nt=nt, mode=tdbem.MODE_IFMM, gmres_rtol=1e-8, gmres_maxit=60,
+                                            guess=guess))
+        if params is not None:
+            S.guess_weights(params)
+        its, el, trajs = [], 0.0, []
+        for p in pulses:
+            S.reset()
+            V = torch.zeros((nt - 1, 1, S.ne), dtype=torch.float64, device="cuda")
+            for a in range(1, nt):
+                S.incident([p], a, V[a - 1])
+            J = torch.zeros_like(V)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st, it = S.march(V, J, with_iters=True)
+            torch.cuda.synchronize()
+            el += time.perf_counter() - t0
+            its.extend(int(x) for x in it[200:])
+            trajs.append(J)
+        r = {"gmres_iters_per_step": float(np.mean(its)), "steps_per_s": len(pulses) * (nt - 1) / el}
+        if guess == tdbem.GUESS_LEARNED:
+            r["learned_guess_taken_steps"] = int(S.guess_used())
+            r["of_steps"] = len(pulses) * (nt - 1)
+        if ref is None:
+            ref = trajs
+        else:
+            num = sum(float(((a - b) ** 2).sum()) for a, b in zip(trajs, ref))
+            den = sum(float((b ** 2).sum()) for b in ref)
+            r["rel_l2_current_vs_extrapolation_run"] = math.sqrt(num / den)
+        out[name] = r
+        S.close()
+        del trajs
+        torch.cuda.empty_cache()
+        print(json.dumps({name: r}), flush=True)
     return out
 
 
@@ -321,6 +451,14 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, run one 512 MiB device copy (counter calibration)")
     ap.add_argument("--last", type=int, default=NT, help="steps marched in all (untimed after the timed ones)")
+    ap.add_argument("--step-loop", action="store_true",
+                    help="time the steps as tdbem_step calls (default: one tdbem_march call for the timed steps)")
+    ap.add_argument("--no-compare-loop", action="store_true",
+                    help="skip the run that times the same steps issued the other way")
+    ap.add_argument("--guess-study", action="store_true",
+                    help="only the learned initial guess on the held-out 20480-triangle ellipsoid (JSON lines)")
+    ap.add_argument("--far-study", action="store_true",
+                    help="only the dense vs Fourier-domain M2L study at p = 4, 6, 8 (JSON lines)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path",
@@ -332,6 +470,12 @@ def main():
     from paper_2303_05006_amd.inputs import workload, C0
 
     torch.cuda.set_device(0)
+    if args.far_study:
+        far_study(torch, tdbem)
+        return
+    if args.guess_study:
+        guess_study(torch, tdbem)
+        return
     name = "sphere20480" if args.nrhs == 1 else "sphere20480x64"
     w = workload(name, n_rhs=args.nrhs)
     nr = len(w.pulses)
@@ -349,7 +493,7 @@ def main():
     for a in range(1, last + 1):
         S.incident(w.pulses, a, V[a - 1])
     traj = torch.zeros((last, nr, ne), dtype=torch.float64, device="cuda") if chosen else None
-    el, iters, ph = march(torch, S, V, lead, K, last, traj)
+    el, iters, ph = march(torch, S, V, lead, K, last, traj, deferred=not args.step_loop)
     prec_fp64 = args.form == "fp64"
     roof, kernels = kernel_rooflines(info, ph, lead, K, nr, prec_fp64, args.form)
     d0 = S.d0_nnz()
@@ -387,13 +531,27 @@ def main():
         "device_gb": info["device_bytes"] / 1e9,
     }
     S.close()
+    if not args.no_compare_loop:
+        # the other way of issuing the same timed steps, on a fresh context:
+        # K tdbem_step calls (a host wait per step) against one tdbem_march
+        Sx, _ = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol)
+        trx = torch.zeros_like(traj) if traj is not None else None
+        elx, itx, _ = march(torch, Sx, V, lead, K, lead + K, trx, deferred=args.step_loop)
+        Sx.close()
+        key = "deferred_march" if args.step_loop else "step_loop"
+        res[key] = {"steps_per_s": K / elx, "ms_per_step": elx / K * 1e3,
+                    "how": "one tdbem_march call" if args.step_loop else f"{K} tdbem_step calls",
+                    "gmres_iters_mean": float(np.mean(itx))}
+        if traj is not None:
+            res[key]["bitwise_equal_currents"] = bool(torch.equal(trx[:lead + K], traj[:lead + K]))
+        del trx
     if chosen:
         # chosen form on the same incident fields: FP32 near values and M2L
         # products, learned initial guess; error of its march against FP64's
         # over every step to the end of the workload
         S2, setup2 = make_solver(torch, tdbem, w, "fp32", "learned", args.rtol)
         traj32 = torch.zeros_like(traj)
-        el2, iters2, ph2 = march(torch, S2, V, lead, K, last, traj32)
+        el2, iters2, ph2 = march(torch, S2, V, lead, K, last, traj32, deferred=not args.step_loop)
         roof2, kernels2 = kernel_rooflines(S2.info(), ph2, lead, K, nr, False, "fp32")
         dn = ((traj32 - traj) ** 2).sum(dim=(1, 2)).sqrt()
         jn = (traj ** 2).sum(dim=(1, 2)).sqrt()
@@ -411,7 +569,7 @@ def main():
     torch.cuda.empty_cache()
     if chosen and not args.no_batched:
         _, Kb = steady_window(lead, args.batched_steps, info["Mt"][2], info["window"], arrival)
-        res["batched"] = batched_runs(torch, tdbem, lead, Kb, args.rtol, K / el)
+        res["batched"] = batched_runs(torch, tdbem, lead, Kb, args.rtol, K / el, deferred=not args.step_loop)
     if args.copy_probe:
         res["copy_probe"] = copy_probe(torch)
     if not args.no_cpu:

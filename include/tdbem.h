@@ -58,8 +58,8 @@ enum { TDBEM_MODE_DIRECT = 0, TDBEM_MODE_IFMM = 1 };
  * the right-hand side are FP64 in every form).  FP64: everything FP64.  FP32:
  * near-field coefficients stored in FP32, M2L operator and products in FP32 on
  * the matrix cores (moments and local expansions FP64).  BF16: near-field
- * coefficients stored in bf16 (FP64 sums); M2L operator and moments rounded to
- * bf16 with FP32 accumulation on the matrix cores.  The far field applies the
+ * coefficients stored in bf16 (FP64 sums), the FP32 M2L (the bf16 matrix-core
+ * M2L is TDBEM_M2L_BF16).  The far field applies the
  * undifferentiated kernels to differenced currents; the window's terms cancel
  * down to the retarded potential, which amplifies rounding by about (window
  * steps)^2: the reduced forms are options whose error is measured. */
@@ -94,8 +94,13 @@ enum { TDBEM_DT2_SPLIT = 0, TDBEM_DT2_KERNEL = 1, TDBEM_DT2_INTERP = 2 };
  * 3.6.1, last paragraph): transformed kernels per offset and lag are set up
  * once, each interval's moments are transformed once, products are diagonal.
  * FFT computes in FP64 (precision must be TDBEM_FP64) and holds (2p)^3 (p+1)
- * complex values per moment vector (20x the dense moments at p = 4). */
-enum { TDBEM_M2L_AUTO = 0, TDBEM_M2L_GENERIC = 1, TDBEM_M2L_FFT = 2 };
+ * complex values per moment vector (20x the dense moments at p = 4).  BF16
+ * (p = 4): the tuned kernels with operator and moments rounded to bf16 on the
+ * 16x16x32 bf16 matrix-core instruction, FP32 accumulation, whatever the
+ * precision form; the far field's cancellation (window terms that grow with
+ * the square of the lag) amplifies its rounding to errors of order one, so it
+ * is a measured option, not an accurate one. */
+enum { TDBEM_M2L_AUTO = 0, TDBEM_M2L_GENERIC = 1, TDBEM_M2L_FFT = 2, TDBEM_M2L_BF16 = 3 };
 /* Z0 solver (Section 2.5): DEVICE, one cooperative kernel per step for every
  * right-hand side; HOST, the same GMRES driven from the host (reference). */
 enum { TDBEM_SOLVER_DEVICE = 0, TDBEM_SOLVER_HOST = 1 };
@@ -129,7 +134,7 @@ typedef struct {
                                  (FAST4/6/8 of Section 4.2) */
     int32_t interp;           /* TDBEM_INTERP_LAGRANGE or TDBEM_INTERP_CHI_TIME */
     int32_t dt2;              /* TDBEM_DT2_SPLIT | TDBEM_DT2_KERNEL | TDBEM_DT2_INTERP */
-    int32_t m2l;              /* TDBEM_M2L_AUTO | TDBEM_M2L_GENERIC | TDBEM_M2L_FFT */
+    int32_t m2l;              /* TDBEM_M2L_AUTO | TDBEM_M2L_GENERIC | TDBEM_M2L_FFT | TDBEM_M2L_BF16 */
     int32_t leaf_max;         /* subdivide a cell while it holds more edges than this (Section 3.4.1) */
     int32_t min_level;        /* subdivide at least down to this level (2) */
     int32_t mu_window;        /* future intervals of the M2L (paper: 8, Section 3.6.1); raised if needed */
@@ -150,6 +155,14 @@ typedef struct {
     int32_t guess;            /* TDBEM_GUESS_EXTRAP (quadratic extrapolation) or _LEARNED */
     int32_t solver;           /* TDBEM_SOLVER_DEVICE or TDBEM_SOLVER_HOST */
     int32_t gmres_blocks;     /* blocks per system of the device solve (0: automatic) */
+    int32_t autotune;         /* 1: at set-up, time the near-field kernel's round shapes (lag steps and pair
+                                 blocks per round) and, for one right-hand side with gmres_blocks = 0, the
+                                 device solve's blocks per system, and keep the fastest (TDBEM_Q_TUNED);
+                                 0: the fixed defaults */
+    int32_t near_kernel;      /* one-rhs near-field kernel: 0 the default (or the autotuner's choice); k >= 1
+                                 forces form k - 1: 0-4 the row kernel with (lag steps, pair blocks) per round
+                                 (2,1) (1,1) (3,1) (2,2) (1,2), 5-6 the per-leaf kernel (the leaf's source
+                                 currents staged in LDS) with 2 or 1 lag steps per round */
     /* late-time stability monitor (Section 4.3): 0 disables.  Once the tested
      * incident field of a right-hand side has fallen below 1e-6 of its largest
      * norm so far (the excitation has passed), a step returns TDBEM_EUNSTABLE
@@ -187,6 +200,24 @@ int tdbem_potentials(tdbem_ctx *ctx, const double *hist_dev, int32_t n_hist, dou
  * J^{alpha-1} out (device); advances alpha.  TDBEM_ENOCONV if the Z0 solve
  * misses the tolerance (the iterate is still returned). */
 int tdbem_step(tdbem_ctx *ctx, const double *V_dev, double *J_dev);
+
+/* n_steps MOT steps in a row (Program 1), the same as n_steps calls of
+ * tdbem_step, without a host wait between them: each step's GMRES status (and
+ * the stability monitor's norms) stays on the device and is read once after
+ * the last step, so the host enqueues the next step while the GPU works.
+ * V_dev [n_steps][n_rhs][N_e] device, the tested incident fields of the steps
+ * alpha .. alpha + n_steps - 1 (read only); J_dev [n_steps][n_rhs][N_e] device,
+ * receives the currents.  status (host int32 [n_steps], may be NULL) receives
+ * each step's code (TDBEM_OK, TDBEM_ENOCONV, TDBEM_EUNSTABLE), iters (host
+ * int32 [n_steps], may be NULL) its GMRES iterations (the largest over the
+ * right-hand sides).  Returns the
+ * first non-OK step code, TDBEM_EHIP if a grid-barrier wait timed out.  Every
+ * step runs (a step that did not converge keeps its last iterate, as
+ * tdbem_step does).  The per-step records are device memory of the context,
+ * grown on demand (16 n_rhs + 16 n_rhs bytes per step).  With the host-driven
+ * solver the steps are taken one at a time. */
+int tdbem_march(tdbem_ctx *ctx, const double *V_dev, double *J_dev, int32_t n_steps, int32_t *status,
+                int32_t *iters);
 
 /* For callers that cannot allocate device memory during the march (code under
  * graph capture, serving loops, harnesses that forbid allocation): the same
@@ -246,9 +277,12 @@ enum {
                                 all pairs (the exact lag support of every pair, as the direct mode stores
                                 it); computed on the device at the first query */
     TDBEM_Q_UNSTABLE = 20,   /* int32 [n_rhs]: 1 where the stability monitor has tripped */
-    TDBEM_Q_WINDOWS = 21     /* int32 [l_max+1]: source intervals per M2L per level, mu + ceil(3 / M_t(l)) (0 above
+    TDBEM_Q_WINDOWS = 21,    /* int32 [l_max+1]: source intervals per M2L per level, mu + ceil(3 / M_t(l)) (0 above
                                 level 2): the window's oldest ceil(3 / M_t) intervals use differences truncated at
                                 the oldest interval's start */
+    TDBEM_Q_TUNED = 22       /* int32 [4]: the near-field form in use (lag steps of 4 lags per round, 64-pair
+                                blocks per round; 0 blocks: the per-leaf kernel), the device solve's blocks per
+                                system (0: automatic) and 1 if the set-up autotuner chose them */
 };
 
 /* Phases timed by tdbem_profile (HIP events on the work stream around each

@@ -1,5 +1,6 @@
 // extern "C" entry points and the marching driver (Program 1).
 #include <algorithm>
+#include <functional>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -72,6 +73,131 @@ bool gmres_coop_launch_static(tdbem_ctx *C, const double *b, double *x, double r
 double *noalloc_scratch(size_t *capacity);
 size_t noalloc_need(const tdbem_ctx *C);
 size_t gmres_coop_work_doubles(int ne, int nrhs);
+void launch_fill(int64_t n, double v, double *p, hipStream_t s);
+int near_variants();
+void near_variant_shape(int v, int *nu, int *nc);
+
+size_t near_leaf_lds_budget();
+
+// The per-leaf form of the one-rhs near field: per leaf cell, its rows (a
+// range in leaf order), the sorted source edges of its rows' pairs, each
+// pair's index in that list, and the lag window [gmin, gmin + gw) its strips
+// cover.  Leaves whose window exceeds the LDS budget keep the row kernel.
+static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const std::vector<int> &nj,
+                              const std::vector<int> &ngl) {
+    const Tree &T = C->T;
+    const size_t jt = C->cfg.precision == TDBEM_FP64 ? sizeof(double) : sizeof(float);
+    const size_t budget = near_leaf_lds_budget() / jt;
+    std::vector<int> r0, r1, soff(1, 0), src, g, loc(nj.size(), 0), fit, rest;
+    size_t maxw = 0;
+    for (int l = 0; l <= T.lmax; ++l) {
+        const Level &Lv = T.lev[l];
+        for (int c = 0; c < Lv.n; ++c) {
+            if (!Lv.leaf[c] || Lv.eend[c] <= Lv.ebeg[c]) continue;
+            const int a = Lv.ebeg[c], b = Lv.eend[c];
+            std::vector<int> list;
+            int gmin = 1 << 30, gmax = -1;
+            for (int q = nrow[a]; q < nrow[b]; ++q) {
+                list.push_back(nj[q]);
+                gmin = std::min(gmin, ngl[q] & 0xffff);
+                gmax = std::max(gmax, (ngl[q] & 0xffff) + (ngl[q] >> 16) - 1);
+            }
+            std::sort(list.begin(), list.end());
+            list.erase(std::unique(list.begin(), list.end()), list.end());
+            const int id = (int)r0.size();
+            r0.push_back(a);
+            r1.push_back(b);
+            const int gw = gmax >= gmin ? gmax - gmin + 1 : 1;
+            g.push_back(gmax >= gmin ? gmin : 2);
+            g.push_back(gw);
+            for (int q = nrow[a]; q < nrow[b]; ++q)
+                loc[q] = (int)(std::lower_bound(list.begin(), list.end(), nj[q]) - list.begin());
+            src.insert(src.end(), list.begin(), list.end());
+            soff.push_back((int)src.size());
+            const size_t w = list.size() * (size_t)gw;
+            if (w <= budget) {
+                fit.push_back(id);
+                maxw = std::max(maxw, w);
+            } else {
+                for (int r = a; r < b; ++r) rest.push_back(r);
+            }
+        }
+    }
+    // the leaves' rows must partition the rows; otherwise every row takes the row kernel
+    size_t covered = 0;
+    for (size_t i = 0; i < r0.size(); ++i) covered += (size_t)(r1[i] - r0[i]);
+    if (covered != (size_t)C->ne) {
+        fit.clear();
+        rest.resize(C->ne);
+        std::iota(rest.begin(), rest.end(), 0);
+    }
+    NearLeaves &NL = C->nleaf;
+    NL.nfit = (int)fit.size();
+    NL.nrest = (int)rest.size();
+    NL.max_window = std::max<size_t>(maxw, 1);
+    NL.d_fit = dupload(C, fit);
+    NL.d_r0 = dupload(C, r0);
+    NL.d_r1 = dupload(C, r1);
+    NL.d_soff = dupload(C, soff);
+    NL.d_src = dupload(C, src);
+    NL.d_g = dupload(C, g);
+    NL.d_loc = dupload(C, loc);
+    NL.d_rest = dupload(C, rest);
+}
+
+// Set-up autotuner: times the candidates on the context's own data and keeps
+// the fastest.  Near field (one rhs): each round shape, 2 warm-up and 5 timed
+// launches of the history sum (the values of the zero ring do not change the
+// work).  Device solve (one rhs, gmres_blocks = 0): 16 Krylov iterations of
+// an unreachable tolerance on b = 1 for each candidate block count, 3 timed
+// solves each.
+static float time_launches(hipStream_t s, int warm, int reps, const std::function<void()> &f) {
+    hipEvent_t e0, e1;
+    TD_HIP(hipEventCreate(&e0));
+    TD_HIP(hipEventCreate(&e1));
+    for (int i = 0; i < warm; ++i) f();
+    TD_HIP(hipEventRecord(e0, s));
+    for (int i = 0; i < reps; ++i) f();
+    TD_HIP(hipEventRecord(e1, s));
+    TD_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    TD_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+
+static void autotune(tdbem_ctx *C) {
+    hipStream_t s = C->stream;
+    if (C->nrhs == 1 && C->near_nnz > 0) {
+        int best = 0;
+        float tbest = 1e30f;
+        for (int v = 0; v < near_variants(); ++v) {
+            C->near_variant = v;
+            const float t = time_launches(s, 2, 5, [&] { launch_near(C, C->ring, C->d_tmp, 1.0, s); });
+            if (t < tbest) { tbest = t; best = v; }
+        }
+        C->near_variant = best;
+    }
+    if (C->nrhs == 1 && C->use_coop && C->cfg.gmres_blocks == 0) {
+        const int cand[] = {0, 64, 96, 128, 160, 192, 256};
+        int best = 0;
+        float tbest = 1e30f;
+        launch_fill(C->ne, 1.0, C->d_rhs, s);
+        for (int nb : cand) {
+            C->gmres_blocks = nb;
+            bool launched = true;
+            const float t = time_launches(s, 1, 3, [&] {
+                launch_fill(C->ne, 0.0, C->d_x, s);
+                launched = launched && gmres_coop_launch(C, C->d_rhs, C->d_x, 0.0, 16, s);
+            });
+            if (launched && t < tbest) { tbest = t; best = nb; }
+        }
+        C->gmres_blocks = best;
+        TD_HIP(hipMemsetAsync(C->d_iflag, 0, 4 * (size_t)C->nrhs * sizeof(int), s));
+    }
+    C->tuned = true;
+}
 
 // weights of the MFIE's time derivative (kd) and of the MFIE (zeta) in the
 // CFIE variants of Section 4.3.1
@@ -151,6 +277,10 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->gmres_rtol >= 0.0, TDBEM_EINVAL, "gmres_rtol must be non-negative");
     TD_REQUIRE(cfg->solver == TDBEM_SOLVER_DEVICE || cfg->solver == TDBEM_SOLVER_HOST, TDBEM_EINVAL, "unknown solver");
     TD_REQUIRE(cfg->gmres_blocks >= 0 && cfg->gmres_blocks <= 256, TDBEM_EINVAL, "gmres_blocks must be in 0..256");
+    TD_REQUIRE(cfg->autotune == 0 || cfg->autotune == 1, TDBEM_EINVAL, "autotune must be 0 or 1");
+    TD_REQUIRE(cfg->near_kernel >= 0 && cfg->near_kernel <= near_variants(), TDBEM_EINVAL,
+               "near_kernel must be 0 (default or tuned) or 1.." + std::to_string(near_variants()));
+    TD_REQUIRE(cfg->near_kernel == 0 || cfg->autotune == 0, TDBEM_EINVAL, "near_kernel and autotune exclude each other");
     TD_REQUIRE(cfg->growth_limit >= 0.0, TDBEM_EINVAL, "growth_limit must be non-negative");
     TD_REQUIRE(cfg->guess == TDBEM_GUESS_EXTRAP || cfg->guess == TDBEM_GUESS_LEARNED, TDBEM_EINVAL, "unknown guess");
     C->stream = (hipStream_t)cfg->stream;
@@ -277,6 +407,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
             for (int l = 0; l < len; ++l) nl[(size_t)i * L + l]++;
         }
     C->near_L = std::max(L, 1);
+    if (C->nrhs == 1) build_near_leaves(C, nrow, nj, ngl);
     C->near_pairs = (int64_t)nj.size();
     C->near_nnz = nnz2;
     C->d_nrow_ptr = dupload(C, nrow);
@@ -328,6 +459,11 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_HIP(hipMemsetAsync(C->d_Jring, 0, (size_t)ne * R * C->nrhs * sizeof(double), s));
     if (C->d_Jring32) TD_HIP(hipMemsetAsync(C->d_Jring32, 0, (size_t)ne * R * C->nrhs * sizeof(float), s));
     TD_HIP(hipStreamSynchronize(s));
+    if (cfg->near_kernel > 0) C->near_variant = cfg->near_kernel - 1;
+    if (cfg->autotune) {
+        autotune(C);
+        TD_HIP(hipStreamSynchronize(s));
+    }
     C->alpha = 1;
     C->fingerprint = fingerprint(C);
     noalloc_scratch(nullptr);       // the allocation-free step's workspace address on this device
@@ -362,8 +498,17 @@ static bool monitor_update(tdbem_ctx *C) {
     return trip;
 }
 
+// Deferred step status (tdbem_march): the device solve's status words and the
+// monitor's norms of step k are copied on the device into record slot k and
+// read by the host once, after the last step.
+struct MarchRec {
+    int *flags = nullptr;       // [steps][n_rhs][4]
+    double *stat = nullptr;     // [steps][n_rhs][2]
+    int k = 0;
+};
+
 static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, const double *Jgiven,
-                     bool noalloc = false) {
+                     bool noalloc = false, MarchRec *rec = nullptr) {
     hipStream_t s = C->stream;
     const int64_t nv = (int64_t)C->ne * C->nrhs;
     int a = C->alpha;
@@ -391,8 +536,18 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
             const bool launched = noalloc
                 ? gmres_coop_launch_static(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s, &dflag)
                 : C->use_coop && gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, maxit, s);
-            TD_REQUIRE(launched || !noalloc, TDBEM_EHIP, "the device cannot run the cooperative solve");
-            if (launched) {
+            TD_REQUIRE(launched || (!noalloc && !rec), TDBEM_EHIP, "the device cannot run the cooperative solve");
+            if (launched && rec) {
+                // deferred: keep this step's status on the device, no host wait
+                const size_t nf = 4 * (size_t)C->nrhs;
+                if (monitor) {
+                    launch_colnorm2(C, C->d_x, C->d_stat, 1, s);
+                    TD_HIP(hipMemcpyAsync(rec->stat + (size_t)rec->k * 2 * C->nrhs, C->d_stat,
+                                          2 * C->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s));
+                }
+                TD_HIP(hipMemcpyAsync(rec->flags + (size_t)rec->k * nf, dflag, nf * sizeof(int),
+                                      hipMemcpyDeviceToDevice, s));
+            } else if (launched) {
                 const size_t nf = 4 * (size_t)C->nrhs;
                 if (monitor) {
                     launch_colnorm2(C, C->d_x, C->d_stat, 1, s);
@@ -422,7 +577,7 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
             }
         }
         if (!ok) rc = TDBEM_ENOCONV;
-        if (monitor && monitor_update(C)) rc = TDBEM_EUNSTABLE;
+        if (monitor && !(rec && C->use_coop) && monitor_update(C)) rc = TDBEM_EUNSTABLE;
     } else {
         launch_gather_in(C, Jgiven, C->d_x, s);
     }
@@ -460,7 +615,7 @@ static uint64_t fingerprint(const tdbem_ctx *C) {
     const double dv[] = {c.dt, c.eps, c.mu, c.theta, c.zeta, c.gmres_rtol, c.growth_limit};
     const int32_t iv[] = {c.nt, c.d, c.cfie, c.n_quad, c.p_s, c.p_t, c.interp, c.dt2, c.m2l, c.leaf_max, c.min_level,
                           c.mu_window, c.box_widen, c.causal_guard, c.mode, c.precision, c.n_rhs, c.gmres_maxit,
-                          c.gmres_restart, c.guess, c.solver, c.gmres_blocks};
+                          c.gmres_restart, c.guess, c.solver, c.gmres_blocks, c.autotune, c.near_kernel};
     h = fnv(h, dv, sizeof(dv));
     return fnv(h, iv, sizeof(iv));
 }
@@ -639,6 +794,80 @@ int tdbem_step_noalloc(tdbem_ctx *C, const double *V, double *J) {
     return rc;
 }
 
+static int march_impl(tdbem_ctx *C, const double *V, double *J, int32_t n_steps, int32_t *status,
+                      int32_t *iters) {
+    int first = TDBEM_OK;
+    const size_t nv = (size_t)C->ne * C->nrhs, nr = C->nrhs;
+    if (!C->use_coop) {
+        // the host-driven solver waits on the host anyway: one step at a time
+        for (int k = 0; k < n_steps; ++k) {
+            const int rc = step_impl(C, V + k * nv, J + k * nv, true, nullptr);
+            if (status) status[k] = rc;
+            if (iters) iters[k] = C->last_iters;
+            if (first == TDBEM_OK) first = rc;
+        }
+    } else {
+        if ((size_t)n_steps > C->march_cap) {
+            if (C->d_march) TD_HIP(hipFree(C->d_march));
+            C->d_march = nullptr;
+            C->march_cap = 0;
+            TD_HIP(hipMalloc(&C->d_march, (size_t)n_steps * nr * (4 * sizeof(int) + 2 * sizeof(double))));
+            C->march_cap = (size_t)n_steps;
+        }
+        MarchRec rec;
+        rec.stat = (double *)C->d_march;
+        rec.flags = (int *)(rec.stat + (size_t)n_steps * 2 * nr);
+        for (int k = 0; k < n_steps; ++k) {
+            rec.k = k;
+            step_impl(C, V + k * nv, J + k * nv, true, nullptr, false, &rec);
+        }
+        std::vector<int> fl((size_t)n_steps * 4 * nr);
+        std::vector<double> st((size_t)n_steps * 2 * nr);
+        if (n_steps > 0) {
+            TD_HIP(hipMemcpyAsync(fl.data(), rec.flags, fl.size() * sizeof(int), hipMemcpyDeviceToHost, C->stream));
+            if (C->cfg.growth_limit > 0.0)
+                TD_HIP(hipMemcpyAsync(st.data(), rec.stat, st.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                      C->stream));
+        }
+        TD_HIP(hipStreamSynchronize(C->stream));
+        bool timeout = false;
+        for (int k = 0; k < n_steps; ++k) {
+            bool ok = true;
+            int its = 0;
+            for (size_t r = 0; r < nr; ++r) {
+                const int *f = &fl[((size_t)k * nr + r) * 4];
+                its = std::max(its, f[0]);
+                ok = ok && f[1] != 0;
+                timeout = timeout || f[2] != 0;
+            }
+            C->last_iters = its;
+            if (iters) iters[k] = its;
+            int rc = ok ? TDBEM_OK : TDBEM_ENOCONV;
+            if (C->cfg.growth_limit > 0.0) {
+                std::copy(st.begin() + (size_t)k * 2 * nr, st.begin() + (size_t)(k + 1) * 2 * nr, C->h_stat);
+                if (monitor_update(C)) rc = TDBEM_EUNSTABLE;
+            }
+            if (status) status[k] = rc;
+            if (first == TDBEM_OK) first = rc;
+        }
+        if (timeout) {
+            TD_HIP(hipMemset(C->d_gbar, 0, (size_t)GMRES_BAR_WORDS * C->nrhs * sizeof(unsigned)));
+            throw Error{TDBEM_EHIP, "device solve: a grid barrier wait timed out"};
+        }
+    }
+    return first;
+}
+
+int tdbem_march(tdbem_ctx *C, const double *V, double *J, int32_t n_steps, int32_t *status, int32_t *iters) {
+    if (!C || !V || !J) { set_error("null argument"); return TDBEM_EINVAL; }
+    if (n_steps < 0) { set_error("n_steps < 0"); return TDBEM_EINVAL; }
+    int first = TDBEM_OK;
+    TD_GUARD({ first = march_impl(C, V, J, n_steps, status, iters); });
+    if (first == TDBEM_ENOCONV) set_error("GMRES did not reach the tolerance in at least one step");
+    if (first == TDBEM_EUNSTABLE) set_error("late-time growth: the current exceeds growth_limit times its norm during the excitation");
+    return first;
+}
+
 int tdbem_reset(tdbem_ctx *C) {
     if (!C) { set_error("null context"); return TDBEM_EINVAL; }
     TD_GUARD({ reset_impl(C); TD_HIP(hipStreamSynchronize(C->stream)); });
@@ -670,6 +899,13 @@ int tdbem_query(const tdbem_ctx *C, int32_t key, void *out) {
         case TDBEM_Q_WINDOWS:
             for (int l = 0; l <= T.lmax; ++l) ((int32_t *)out)[l] = l < (int)C->windows.size() ? C->windows[l] : 0;
             break;
+        case TDBEM_Q_TUNED: {
+            int nu = 0, nc = 0;
+            near_variant_shape(C->near_variant, &nu, &nc);
+            int32_t *o = (int32_t *)out;
+            o[0] = nu; o[1] = nc; o[2] = C->gmres_blocks; o[3] = C->tuned ? 1 : 0;
+            break;
+        }
         case TDBEM_Q_UNSTABLE:
             for (int r = 0; r < C->nrhs; ++r) ((int32_t *)out)[r] = C->mon_trip[r];
             break;
@@ -768,6 +1004,7 @@ void tdbem_destroy(tdbem_ctx *C) {
     ifmm_destroy(C);
     guess_destroy(C);
     for (void *p : C->allocs) (void)hipFree(p);
+    if (C->d_march) (void)hipFree(C->d_march);
     if (C->h_scal) (void)hipHostFree(C->h_scal);
     if (C->h_iflag) (void)hipHostFree(C->h_iflag);
     if (C->h_stat) (void)hipHostFree(C->h_stat);

@@ -45,6 +45,7 @@ struct FarState {
     int P = 4, NS = 64, NN = 256;   // interpolation points per axis and in time, P^3, P^4
     bool generic_m2l = false;       // dense M2L with operators formed per lane (any P)
     bool fft_m2l = false;           // M2L through the 4-D Fourier transform
+    bool bf16_m2l = false;          // the tuned p = 4 M2L with bf16 operands
     int64_t NF = 0;                 // transformed values per vector: (2P)^3 (P + 1)
     double2 *fft_s1 = nullptr, *fft_s2 = nullptr;   // transform scratch
     int lmax = 0, FR = 0, nrhs = 1;

@@ -156,8 +156,8 @@ void ifmm_setup(tdbem_ctx *C) {
     const int P = C->cfg.p_s;
     TD_REQUIRE(C->cfg.p_t == P && (P == 4 || P == 6 || P == 8), TDBEM_EINVAL,
                "the far field is built for p_s = p_t = 4, 6 or 8");
-    TD_REQUIRE(C->cfg.m2l == TDBEM_M2L_AUTO || C->cfg.m2l == TDBEM_M2L_GENERIC || C->cfg.m2l == TDBEM_M2L_FFT,
-               TDBEM_EINVAL, "unknown M2L kernel");
+    TD_REQUIRE(C->cfg.m2l >= TDBEM_M2L_AUTO && C->cfg.m2l <= TDBEM_M2L_BF16, TDBEM_EINVAL, "unknown M2L kernel");
+    TD_REQUIRE(C->cfg.m2l != TDBEM_M2L_BF16 || P == 4, TDBEM_EINVAL, "the bf16 M2L is built for p_s = p_t = 4");
     TD_REQUIRE(C->cfg.m2l != TDBEM_M2L_FFT || C->cfg.precision == TDBEM_FP64, TDBEM_EINVAL,
                "the Fourier-domain M2L computes in FP64 (precision must be TDBEM_FP64)");
     TD_REQUIRE(T.lmax >= 2, TDBEM_EINVAL, "IFMM needs at least two levels below the root");
@@ -167,6 +167,7 @@ void ifmm_setup(tdbem_ctx *C) {
     F->NS = P * P * P;
     F->NN = F->NS * P;
     F->fft_m2l = C->cfg.m2l == TDBEM_M2L_FFT;
+    F->bf16_m2l = C->cfg.m2l == TDBEM_M2L_BF16;
     F->generic_m2l = !F->fft_m2l && (P != 4 || C->cfg.m2l == TDBEM_M2L_GENERIC);
     const int NS = F->NS, NN = F->NN;
     const int interp = C->cfg.interp;
@@ -261,11 +262,12 @@ void ifmm_setup(tdbem_ctx *C) {
         FL.child_beg = fup(C, L.child_beg);
         FL.child_end = fup(C, L.child_end);
         FL.MM = falloc<double>(C, (size_t)L.n * FL.WR * FL.NV * NCH * nr * NN);
+        // reduced copies of the moments, written by P2M / M2M: FP32 for the
+        // reduced forms' tuned M2L, bf16 for the bf16 M2L
         const bool tuned = !F->generic_m2l && !F->fft_m2l;
-        if (tuned && C->cfg.precision == TDBEM_FP32)
+        if (tuned && !F->bf16_m2l && C->cfg.precision != TDBEM_FP64)
             FL.MM32 = falloc<float>(C, (size_t)L.n * FL.WR * FL.NV * NCH * nr * NN);
-        if (tuned && C->cfg.precision == TDBEM_BF16)
-            FL.MM16 = falloc<unsigned short>(C, (size_t)L.n * FL.WR * FL.NV * NCH * nr * NN);
+        if (F->bf16_m2l) FL.MM16 = falloc<unsigned short>(C, (size_t)L.n * FL.WR * FL.NV * NCH * nr * NN);
         FL.LC = falloc<double>(C, (size_t)L.n * NCH * nr * NN);
         FL.PEND = falloc<double>(C, (size_t)L.n * 2 * NCH * nr * NN);
         // time tables: targets t = (k+1) d_t + q dt, q = 1..M, in the target interval
@@ -845,8 +847,8 @@ static void m2l_level(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
         return;
     }
     if (P == 4 && !C->far->generic_m2l) {
-        if (f64) m2l_p4_launch<double>(C, FL, k, s);
-        else if (C->cfg.precision == TDBEM_BF16) m2l_bf16_launch(C, FL, k, s);
+        if (C->far->bf16_m2l) m2l_bf16_launch(C, FL, k, s);
+        else if (f64) m2l_p4_launch<double>(C, FL, k, s);
         else m2l_p4_launch<float>(C, FL, k, s);
     } else {
         if (f64) m2l_gen_launch<P, double>(C, FL, k, s); else m2l_gen_launch<P, float>(C, FL, k, s);

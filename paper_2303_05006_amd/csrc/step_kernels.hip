@@ -146,6 +146,115 @@ __global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, cons
     if (lane == 0) out[row] = acc;
 }
 
+// Per-leaf form of the one-rhs history sum: every row of a leaf pairs with the
+// same source edges (the edges of the leaf's near cells), so a block per leaf
+// first stages those sources' current windows (the slots of lags gmin ..
+// gmin + gw - 1 before alpha) in LDS with coalesced ring-row loads, then sums
+// its rows exactly like k_near_jds1 with the currents read from LDS: only the
+// coefficients and the pair metadata stream from HBM.  Pair q's source is
+// loc[q], its index in the leaf's source list.  Leaves whose window does not
+// fit the LDS budget take k_near_jds1 (their rows are listed separately).
+static constexpr int NEAR_LEAF_THREADS = 512;            // 8 wavefronts share one leaf's window
+static constexpr size_t NEAR_LEAF_LDS = 128 * 1024;     // window budget in bytes (one block per CU)
+
+template <typename VT, typename JT, int NU>
+__global__ void __launch_bounds__(NEAR_LEAF_THREADS) k_near_leaf(const int *__restrict__ leaf_id, const int *__restrict__ leaf_r0,
+                                                   const int *__restrict__ leaf_r1, const int *__restrict__ leaf_soff,
+                                                   const int *__restrict__ leaf_src, const int *__restrict__ leaf_g,
+                                                   const int *__restrict__ row_ptr,
+                                                   const int64_t *__restrict__ row_vbase, const int *__restrict__ nl,
+                                                   int L, const int *__restrict__ ploc, const int *__restrict__ pgl,
+                                                   const VT *__restrict__ val, const JT *__restrict__ ring,
+                                                   int ring_mask, int alpha, double *__restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char near_lds[];
+    JT *Jw = reinterpret_cast<JT *>(near_lds);
+    __shared__ int offs[NEAR_LEAF_THREADS / 64][NEAR_LMAX];
+    const int lf = leaf_id[blockIdx.x];
+    const int r0 = leaf_r0[lf], r1 = leaf_r1[lf];
+    const int s0 = leaf_soff[lf], ns = leaf_soff[lf + 1] - s0;
+    const int gmin = leaf_g[2 * lf], gw = leaf_g[2 * lf + 1];
+    const int R = ring_mask + 1;
+    // stage: Jw[s][w] = J at slot alpha - gmin - w of source s
+    for (int e = threadIdx.x; e < ns * gw; e += blockDim.x) {
+        const int sl = e / gw, w = e % gw;
+        Jw[e] = ring[(size_t)leaf_src[s0 + sl] * R + ((alpha - gmin - w) & ring_mask)];
+    }
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int sub = lane & 3, pg = lane >> 2;
+    for (int row = r0 + wv; row < r1; row += NEAR_LEAF_THREADS / 64) {
+        int *off = offs[wv];
+        near_offsets(nl + (size_t)row * L, L, lane, off);
+        const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
+        const VT *v = val + row_vbase[row];
+        double acc = 0.0;
+        for (int c0 = 0; c0 < np; c0 += 64) {
+            const int p = c0 + lane;
+            const int mloc = p < np ? ploc[pb + p] : 0, mgl = p < np ? pgl[pb + p] : 0;
+            const int cnt = min(64, np - c0);
+            const int lmax = __shfl(mgl, 0, 64) >> 16;
+            int jb[4], len[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int q = 16 * g + pg;
+                const int lo = __shfl(mloc, q, 64), gl = __shfl(mgl, q, 64);
+                jb[g] = lo * gw + (gl & 0xffff) - gmin;    // window index of the strip's first lag
+                len[g] = q < cnt ? gl >> 16 : 0;
+            }
+            for (int lb = 0; lb < lmax; lb += 4 * NU) {
+                double a[4][NU], x[4][NU];
+#pragma unroll
+                for (int t = 0; t < NU; ++t) {
+                    const int l = lb + 4 * t + sub;
+                    const int ol = l < L ? off[l] : 0;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const bool ok = l < len[g];
+                        a[g][t] = ok ? (double)v[ol + c0 + 16 * g + pg] : 0.0;
+                        x[g][t] = ok ? (double)Jw[jb[g] + l] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < NU; ++t)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) acc += a[g][t] * x[g][t];
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) out[row] = acc;
+    }
+}
+
+// the rows the per-leaf form leaves to the row kernel: one wavefront per listed row
+template <typename VT, typename JT>
+__global__ void __launch_bounds__(256) k_near_rows_listed(int nrows, const int *__restrict__ rows,
+                                                          const int *__restrict__ row_ptr,
+                                                          const int64_t *__restrict__ row_vbase,
+                                                          const int *__restrict__ nl, int L,
+                                                          const int *__restrict__ pj, const int *__restrict__ pgl,
+                                                          const VT *__restrict__ val, const JT *__restrict__ ring,
+                                                          int ring_mask, int alpha, double *__restrict__ out) {
+    __shared__ int offs[4][NEAR_LMAX];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wv;
+    if (idx >= nrows) return;
+    const int row = rows[idx];
+    int *off = offs[wv];
+    near_offsets(nl + (size_t)row * L, L, lane, off);
+    const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
+    const VT *v = val + row_vbase[row];
+    const int R = ring_mask + 1;
+    double acc = 0.0;
+    for (int p = lane; p < np; p += 64) {
+        const int j = pj[pb + p], gl = pgl[pb + p];
+        const int g0 = gl & 0xffff, len = gl >> 16;
+        for (int l = 0; l < len; ++l)
+            acc += (double)v[off[l] + p] * (double)ring[(size_t)j * R + ((alpha - g0 - l) & ring_mask)];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) out[row] = acc;
+}
+
 // batched right-hand sides: one wavefront per (row, group of 64 rhs); lanes are rhs
 template <typename VT, typename JT>
 __global__ void __launch_bounds__(256) k_near_jdsN(int ne, int nrhs, const int *__restrict__ row_ptr,
@@ -208,12 +317,55 @@ void launch_near_to_jds(const tdbem_ctx *C, const int64_t *src_off, const double
     TD_HIP(hipGetLastError());
 }
 
+// round shapes of the one-rhs kernel: (lag steps of 4 lags, 64-pair blocks)
+// per round; variant 0 is the default (NEAR_NU, NEAR_NC); variants 5 and 6
+// are the per-leaf form with 2 and 1 lag steps (pair blocks reported as 0)
+static constexpr int NEAR_NVAR = 7;
+static const int near_var_nu[NEAR_NVAR] = {NEAR_NU, 1, 3, 2, 1, 2, 1};
+static const int near_var_nc[NEAR_NVAR] = {NEAR_NC, 1, 1, 2, 2, 0, 0};
+int near_variants() { return NEAR_NVAR; }
+size_t near_leaf_lds_budget() { return NEAR_LEAF_LDS; }
+void near_variant_shape(int v, int *nu, int *nc) { *nu = near_var_nu[v]; *nc = near_var_nc[v]; }
+
+template <typename VT, typename JT, int NU, int NC>
+static void launch_jds1(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
+    unsigned nb = grid8((C->ne + 3) / 4);
+    hipLaunchKernelGGL((k_near_jds1<VT, JT, NU, NC>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
+                       C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
+}
+
+template <typename VT, typename JT, int NU>
+static void launch_leaf(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
+    const NearLeaves &NL = C->nleaf;
+    static bool lds_set = false;          // windows above 64 KB need the kernel's LDS limit raised
+    if (!lds_set) {
+        TD_HIP(hipFuncSetAttribute((const void *)k_near_leaf<VT, JT, NU>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)NEAR_LEAF_LDS));
+        lds_set = true;
+    }
+    if (NL.nfit > 0)
+        hipLaunchKernelGGL((k_near_leaf<VT, JT, NU>), dim3(NL.nfit), dim3(NEAR_LEAF_THREADS),
+                           NL.max_window * sizeof(JT), s,
+                           NL.d_fit, NL.d_r0, NL.d_r1, NL.d_soff, NL.d_src, NL.d_g, C->d_nrow_ptr, C->d_nrow_vbase,
+                           C->d_nl, C->near_L, NL.d_loc, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
+    if (NL.nrest > 0)
+        hipLaunchKernelGGL((k_near_rows_listed<VT, JT>), dim3((NL.nrest + 3) / 4), dim3(256), 0, s, NL.nrest,
+                           NL.d_rest, C->d_nrow_ptr, C->d_nrow_vbase, C->d_nl, C->near_L, C->d_npair_j,
+                           C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
+}
+
 template <typename VT, typename JT>
 static void launch_near_t(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
     if (C->nrhs == 1) {
-        unsigned nb = grid8((C->ne + 3) / 4);
-        hipLaunchKernelGGL((k_near_jds1<VT, JT, NEAR_NU, NEAR_NC>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
-                           C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
+        switch (C->near_variant) {
+            case 5: launch_leaf<VT, JT, 2>(C, val, ring, alpha, out, s); break;
+            case 6: launch_leaf<VT, JT, 1>(C, val, ring, alpha, out, s); break;
+            case 1: launch_jds1<VT, JT, 1, 1>(C, val, ring, alpha, out, s); break;
+            case 2: launch_jds1<VT, JT, 3, 1>(C, val, ring, alpha, out, s); break;
+            case 3: launch_jds1<VT, JT, 2, 2>(C, val, ring, alpha, out, s); break;
+            case 4: launch_jds1<VT, JT, 1, 2>(C, val, ring, alpha, out, s); break;
+            default: launch_jds1<VT, JT, NEAR_NU, NEAR_NC>(C, val, ring, alpha, out, s); break;
+        }
     } else {
         int ngrp = (C->nrhs + 63) / 64;
         unsigned nb = grid8(((int64_t)C->ne * ngrp + 3) / 4);
@@ -251,6 +403,11 @@ __global__ void k_scatter_out(int ne, int nrhs, const int *perm, const double *s
     for (int r = 0; r < nrhs; ++r) dst[(size_t)r * ne + e] = src[(size_t)p * nrhs + r];
 }
 // y = a*x + b*y over n values
+__global__ void k_fill(int64_t n, double v, double *p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_axpby(int64_t n, double a, const double *x, double b, double *y) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) y[k] = a * x[k] + b * y[k];
@@ -364,6 +521,11 @@ void launch_scatter_out(const tdbem_ctx *C, const double *src, double *dst, hipS
     hipLaunchKernelGGL(k_scatter_out, dim3(nblk(C->ne, 256)), dim3(256), 0, s, C->ne, C->nrhs, C->d_perm, src, dst);
     TD_HIP(hipGetLastError());
 }
+void launch_fill(int64_t n, double v, double *p, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(nblk(n, 256)), dim3(256), 0, s, n, v, p);
+    TD_HIP(hipGetLastError());
+}
+
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s) {
     hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 256)), dim3(256), 0, s, n, a, x, b, y);
     TD_HIP(hipGetLastError());

@@ -107,6 +107,22 @@ constexpr int GMRES_BAR_WORDS = 2 * 1024;
 
 }  // namespace tdbem
 
+namespace tdbem {
+// the per-leaf form of the one-rhs near field: leaves whose sources' current
+// windows fit the LDS budget, their source lists and windows, and the rows
+// of the other leaves
+struct NearLeaves {
+    int nfit = 0, nrest = 0;
+    size_t max_window = 0;          // largest staged window (values)
+    int *d_fit = nullptr;           // [nfit] leaf ids taking the per-leaf kernel
+    int *d_r0 = nullptr, *d_r1 = nullptr;   // [leaves] row range
+    int *d_soff = nullptr, *d_src = nullptr;  // [leaves+1] offsets, source edges (leaf order)
+    int *d_g = nullptr;             // [leaves][2] first lag and window length
+    int *d_loc = nullptr;           // [pairs] source index in the pair's leaf list
+    int *d_rest = nullptr;          // [nrest] rows left to the row kernel
+};
+}  // namespace tdbem
+
 struct tdbem_ctx {
     tdbem_config cfg;
     hipStream_t stream = nullptr;
@@ -161,9 +177,14 @@ struct tdbem_ctx {
     double *d_pulse = nullptr;      // [nrhs][11]
     double *d_tmp = nullptr;        // [ne][nrhs] scratch (canonical order io)
     int *d_iflag = nullptr;         // device solver status per rhs: iterations, converged, barrier timeout
+    void *d_march = nullptr;        // deferred step records of tdbem_march (grown on demand)
+    size_t march_cap = 0;           // steps the records hold
     int *h_iflag = nullptr;         // pinned host mirror
     unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve, GMRES_BAR_WORDS per rhs
     int gmres_blocks = 0;           // blocks per system of the cooperative solve (0: automatic)
+    int near_variant = 0;           // round shape of the one-rhs near-field kernel (set-up autotuner)
+    tdbem::NearLeaves nleaf;        // the per-leaf near-field form (built for one rhs)
+    bool tuned = false;             // the set-up autotuner chose near_variant / gmres_blocks
     bool use_coop = true;           // device-resident solve
     // late-time stability monitor: per rhs, squared norms of V and J of the
     // step ([rhs][2], device and pinned host), largest |V| so far, largest |J|

@@ -25,13 +25,14 @@ GUESS_EXTRAP, GUESS_LEARNED = 0, 1
 CFIE1, CFIE2, CFIE3 = 1, 2, 3
 DT2_SPLIT, DT2_KERNEL, DT2_INTERP = 0, 1, 2
 SOLVER_DEVICE, SOLVER_HOST = 0, 1
-M2L_AUTO, M2L_GENERIC, M2L_FFT = 0, 1, 2
+M2L_AUTO, M2L_GENERIC, M2L_FFT, M2L_BF16 = 0, 1, 2, 3
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
     Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT, Q_GUESS_USED, \
-    Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS = range(22)
+    Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS, Q_TUNED = range(23)
 PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
-EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_step_noalloc",
+EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_march",
+           "tdbem_step_noalloc",
            "tdbem_reset",
            "tdbem_checkpoint", "tdbem_restore", "tdbem_query", "tdbem_near_rows", "tdbem_profile", "tdbem_guess_weights", "tdbem_guess_capture",
            "tdbem_guess_grad", "tdbem_guess_adam",
@@ -63,6 +64,7 @@ class _Config(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
                 ("gmres_rtol", ctypes.c_double), ("gmres_maxit", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("guess", ctypes.c_int32), ("solver", ctypes.c_int32), ("gmres_blocks", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("near_kernel", ctypes.c_int32),
                 ("growth_limit", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
@@ -79,6 +81,7 @@ def load():
         L.tdbem_potentials.argtypes = [P, P, i32, P]
         L.tdbem_step.argtypes = [P, P, P]
         L.tdbem_step_noalloc.argtypes = [P, P, P]
+        L.tdbem_march.argtypes = [P, P, P, i32, P, P]
         L.tdbem_reset.argtypes = [P]
         L.tdbem_checkpoint.argtypes = [P, P, ctypes.POINTER(ctypes.c_size_t)]
         L.tdbem_restore.argtypes = [P, P, ctypes.c_size_t]
@@ -133,6 +136,8 @@ class Config:
     guess: int = GUESS_EXTRAP
     solver: int = SOLVER_DEVICE
     gmres_blocks: int = 0
+    autotune: int = 0
+    near_kernel: int = 0
     growth_limit: float = 0.0
 
 
@@ -173,6 +178,7 @@ class Solver:
                     cfg.p_s, cfg.p_t, cfg.interp, cfg.dt2, cfg.m2l, cfg.leaf_max, cfg.min_level, cfg.mu_window,
                     cfg.box_widen, cfg.causal_guard, cfg.mode, cfg.precision, cfg.n_rhs,
                     cfg.gmres_rtol, cfg.gmres_maxit, cfg.gmres_restart, cfg.guess, cfg.solver, cfg.gmres_blocks,
+                    cfg.autotune, cfg.near_kernel,
                     cfg.growth_limit, ctypes.c_void_p(s.cuda_stream))
         h = ctypes.c_void_p()
         _check(L.tdbem_setup(ctypes.byref(m), ctypes.byref(c), ctypes.byref(h)))
@@ -224,6 +230,18 @@ class Solver:
 
     def step(self, V, J):
         _check(load().tdbem_step(self._h, _ptr(V), _ptr(J)))
+
+    def march(self, V, J, n_steps=None, with_iters=False):
+        """tdbem_march: V, J [n_steps][n_rhs][N_e] (or [n_steps][N_e]) device
+        tensors; returns (code, per-step codes[, per-step GMRES iterations])."""
+        n = V.shape[0] if n_steps is None else n_steps
+        st = np.zeros(max(n, 1), dtype=np.int32)
+        it = np.zeros(max(n, 1), dtype=np.int32)
+        rc = load().tdbem_march(self._h, _ptr(V), _ptr(J), int(n), st.ctypes.data_as(ctypes.c_void_p),
+                                it.ctypes.data_as(ctypes.c_void_p))
+        if rc not in (OK, ENOCONV, EUNSTABLE):
+            _check(rc)
+        return (rc, st[:n], it[:n]) if with_iters else (rc, st[:n])
 
     def step_noalloc(self, V, J):
         """tdbem_step with the solve's workspace in the library's static array."""

@@ -219,6 +219,44 @@ def test_precision_forms_potentials(setup, prec, tol):
     B.close()
 
 
+def test_bf16_m2l_rounding_level_and_batched_equals_single(setup):
+    """The bf16 matrix-core M2L (m2l = BF16: operator and moments in bf16,
+    FP32 accumulation).  Its error against near + all-interval far of the
+    oracles is the FP32 M2L's error scaled by the ratio of the unit roundoffs
+    (2^16): both are operand rounding amplified by the same cancellation (15
+    and 2.5e-4 measured).  Target-major (2 rhs) and offset-major (1 rhs) bf16
+    kernels share the roundings and differ only in the order of their FP32
+    sums, amplified alike: within the FP32 forms' 2e-3."""
+    torch = _torch()
+    m, S, F, Z, near, dt = setup
+    ref, _ = _near_plus_far(S, Z, near, 97)
+    errs = {}
+    outs = {}
+    for name, kw in (("fp32", dict(precision=tdbem.FP32)), ("bf16", dict(m2l=tdbem.M2L_BF16))):
+        B = _solver(dt, S.interp, **kw)
+        out = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+        B.potentials(torch.tensor(HIST, device="cuda"), 97, out)
+        outs[name] = out.cpu().numpy()
+        errs[name] = np.abs(outs[name] - ref).max() / np.abs(ref).max()
+        B.close()
+    ratio = errs["bf16"] / (errs["fp32"] * 2.0 ** 16)
+    print(f"bf16 M2L {errs['bf16']:.2e}, FP32 M2L {errs['fp32']:.2e}: ratio to the roundoff ratio {ratio:.2f}")
+    assert 0.1 < ratio < 10
+    B2 = _solver(dt, S.interp, m2l=tdbem.M2L_BF16, n_rhs=2)
+    hist2 = np.stack([HIST, HIST[::-1].copy()], axis=1)
+    out2 = torch.zeros((2, m.ne), dtype=torch.float64, device="cuda")
+    B2.potentials(torch.tensor(hist2, device="cuda"), 97, out2)
+    B1 = _solver(dt, S.interp, m2l=tdbem.M2L_BF16)
+    for r in range(2):
+        o1 = torch.zeros(m.ne, dtype=torch.float64, device="cuda")
+        B1.potentials(torch.tensor(np.ascontiguousarray(hist2[:, r]), device="cuda"), 97, o1)
+        rel = np.abs(out2[r].cpu().numpy() - o1.cpu().numpy()).max() / np.abs(o1.cpu().numpy()).max()
+        print(f"bf16 M2L, rhs {r}: target-major vs offset-major {rel:.2e}")
+        assert rel < 2e-3
+    B1.close()
+    B2.close()
+
+
 def test_fp32_form_batched_equals_single(setup):
     """FP32 form: target-major batched M2L against offset-major single runs."""
     torch = _torch()

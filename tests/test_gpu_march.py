@@ -1,0 +1,72 @@
+"""Steps without a host wait between them (tdbem_march), through the C ABI.
+
+tdbem_march runs the same kernels in the same order as consecutive tdbem_step
+calls and only defers the reading of each step's solver status and monitor
+norms to the end, so its currents are bitwise those of the step loop; its
+per-step codes are those the step loop returns.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from paper_2303_05006_amd import tdbem
+from paper_2303_05006_amd.inputs import icosphere, gaussian_pulse, C0
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible to torch")
+    return torch
+
+
+def _both(cfg, nr, nt, level=2):
+    torch = _torch()
+    v, f = icosphere(level)
+    A = tdbem.Solver(v, f, tdbem.Config(**cfg, n_rhs=nr))
+    B = tdbem.Solver(v, f, tdbem.Config(**cfg, n_rhs=nr))
+    pulses = [gaussian_pulse(150e6 + 30e6 * r, 100e6) for r in range(nr)]
+    shape = (nr, A.ne)
+    V = torch.zeros((nt - 1,) + shape, dtype=torch.float64, device="cuda")
+    for a in range(1, nt):
+        A.incident(pulses, a, V[a - 1])
+    J = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    ref, codes = [], []
+    for a in range(1, nt):
+        codes.append(A.step_rc(V[a - 1], J))
+        ref.append(J.clone())
+    Jm = torch.zeros_like(V)
+    # two calls: steps 1..k, then the rest (the records are reused and grown)
+    k = (nt - 1) // 3
+    rc1, st1 = B.march(V[:k], Jm[:k])
+    rc2, st2 = B.march(V[k:], Jm[k:])
+    A.close()
+    B.close()
+    return torch.stack(ref), Jm, codes, list(st1) + list(st2), (rc1, rc2)
+
+
+@pytest.mark.parametrize("mode,nr", [(tdbem.MODE_DIRECT, 1), (tdbem.MODE_IFMM, 1), (tdbem.MODE_IFMM, 2)])
+def test_march_equals_step_loop_bitwise(mode, nr):
+    cfg = dict(dt=0.078 / C0, mode=mode, leaf_max=6, gmres_rtol=1e-12, gmres_maxit=200)
+    ref, got, codes, st, rcs = _both(cfg, nr, 90)
+    assert all(c == tdbem.OK for c in codes) and all(c == tdbem.OK for c in st) and rcs == (tdbem.OK, tdbem.OK)
+    assert _torch().equal(ref, got)
+
+
+def test_march_reports_per_step_codes_like_the_step_loop():
+    """gmres_maxit = 1 at rtol 1e-14: steps that do not converge return
+    ENOCONV in both; growth_limit 1e-30: the monitor trips from the same step."""
+    cfg = dict(dt=0.5e-9, mode=tdbem.MODE_DIRECT, gmres_rtol=1e-14, gmres_maxit=1)
+    ref, got, codes, st, rcs = _both(cfg, 1, 30, level=1)
+    assert codes == st
+    assert tdbem.ENOCONV in codes
+    assert _torch().equal(ref, got)
+    # the 150 MHz pulse has passed the sphere by about step 115 of 0.5 ns
+    cfg = dict(dt=0.5e-9, mode=tdbem.MODE_DIRECT, gmres_rtol=1e-12, growth_limit=1e-30)
+    nt = 160
+    ref, got, codes, st, rcs = _both(cfg, 1, nt, level=1)
+    assert codes == st
+    assert tdbem.EUNSTABLE in codes
+    first = codes.index(tdbem.EUNSTABLE)
+    assert rcs[0 if first < (nt - 1) // 3 else 1] == tdbem.EUNSTABLE

@@ -211,7 +211,8 @@ def test_all_pairs_count_and_config_in_effect():
 @pytest.mark.parametrize("field,value", [("cfie", 0), ("cfie", 4), ("n_quad", 6), ("gmres_restart", 0),
                                          ("gmres_restart", 33), ("dt2", 3), ("solver", 2), ("growth_limit", -1.0),
                                          ("box_widen", 2), ("p_s", 5), ("p_s", 6), ("m2l", 7),
-                                         ("m2l+fp32", tdbem.M2L_FFT)])
+                                         ("m2l+fp32", tdbem.M2L_FFT), ("m2l+p6", tdbem.M2L_BF16),
+                                         ("near_kernel", 8), ("autotune", 2)])
 def test_invalid_configuration_fields(field, value):
     """(p_s = 6 with p_t = 4: the orders must agree; the Fourier-domain M2L with
     FP32.)"""
@@ -220,7 +221,67 @@ def test_invalid_configuration_fields(field, value):
     cfg = tdbem.Config(dt=0.1 / C0, mode=tdbem.MODE_IFMM, leaf_max=6)
     if field == "m2l+fp32":               # the Fourier-domain M2L is FP64 only
         field, cfg.precision = "m2l", tdbem.FP32
+    if field == "m2l+p6":                 # the bf16 M2L is built for p = 4
+        field, cfg.p_s, cfg.p_t = "m2l", 6, 6
     setattr(cfg, field, value)
     with pytest.raises(tdbem.TdbemError) as e:
         tdbem.Solver(v, f, cfg)
     assert e.value.code == tdbem.EINVAL
+
+
+@pytest.mark.parametrize("mode", [tdbem.MODE_DIRECT, tdbem.MODE_IFMM])
+def test_autotuned_context_marches_like_the_default(mode):
+    """autotune = 1 picks a near-field round shape and the device solve's
+    blocks per system by timing them at set-up (TDBEM_Q_TUNED); the march is
+    the same up to the order of FP64 sums."""
+    torch = _torch()
+    v, f = icosphere(3)
+    dt = 0.05 / C0
+    cfg = dict(dt=dt, mode=mode, leaf_max=16, gmres_rtol=1e-12, gmres_maxit=200)
+    A = tdbem.Solver(v, f, tdbem.Config(**cfg))
+    B = tdbem.Solver(v, f, tdbem.Config(**cfg, autotune=1))
+    tuned = B.query_array(tdbem.Q_TUNED, 4, np.int32)
+    print(f"tuned: near round {tuned[0]} lag steps x {tuned[1]} pair blocks, solve blocks {tuned[2]}")
+    assert tuned[3] == 1 and (tuned[0], tuned[1]) in {(2, 1), (1, 1), (3, 1), (2, 2), (1, 2), (2, 0), (1, 0)}
+    assert tuned[2] in (0, 64, 96, 128, 160, 192, 256)
+    assert A.query_array(tdbem.Q_TUNED, 4, np.int32).tolist() == [2, 1, 0, 0]
+    pulse = gaussian_pulse(300e6, 200e6)
+    Ja = _march(A, [pulse], 80, torch).cpu().numpy()
+    Jb = _march(B, [pulse], 80, torch).cpu().numpy()
+    rel = np.abs(Ja - Jb).max() / np.abs(Ja).max()
+    print(f"tuned vs default march: {rel:.2e}")
+    assert rel < 1e-10
+    A.close()
+    B.close()
+
+
+@pytest.mark.parametrize("mode,prec,level", [(tdbem.MODE_IFMM, tdbem.FP64, 2), (tdbem.MODE_IFMM, tdbem.FP32, 2),
+                                             (tdbem.MODE_DIRECT, tdbem.FP64, 3)])
+def test_near_field_forms_agree_bitwise(mode, prec, level):
+    """Every one-rhs near-field form (near_kernel 1..7) on the same history: the
+    per-leaf kernel (forms 5, 6: the leaf's source currents staged in LDS) sums
+    in the row kernel's order (forms 0, 1 with the same lag steps), so their
+    potentials are bitwise equal; the other round shapes agree to FP64
+    rounding.  In the direct mode every pair is near and the leaves' windows
+    exceed the LDS budget, so the per-leaf forms hand their rows to the row
+    kernel."""
+    torch = _torch()
+    v, f = icosphere(level)
+    dt = (CDT if mode == tdbem.MODE_IFMM else 0.075) / C0
+    ne = 3 * len(f) // 2
+    hist = torch.tensor(np.random.default_rng(9).standard_normal((40, ne)), device="cuda")
+    outs = {}
+    for k in range(1, 8):
+        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=mode, precision=prec, leaf_max=LEAF, near_kernel=k))
+        assert S.query_array(tdbem.Q_TUNED, 4, np.int32)[3] == 0
+        o = torch.zeros(ne, dtype=torch.float64, device="cuda")
+        S.potentials(hist, 40, o)
+        outs[k - 1] = o
+        S.close()
+    if mode == tdbem.MODE_IFMM:
+        assert torch.equal(outs[5], outs[0]) and torch.equal(outs[6], outs[1])
+    else:                                 # both hand every row to the listed-row kernel
+        assert torch.equal(outs[5], outs[6])
+    ref = outs[0].abs().max()
+    for k in range(1, 7):
+        assert float((outs[k] - outs[0]).abs().max() / ref) < 1e-13

@@ -34,7 +34,7 @@ def near_visits(lens, NU, NC):
     return seen
 
 
-@pytest.mark.parametrize("NU,NC", [(2, 1), (1, 2), (2, 2), (3, 1)])
+@pytest.mark.parametrize("NU,NC", [(2, 1), (1, 1), (1, 2), (2, 2), (3, 1)])
 @pytest.mark.parametrize("seed", range(4))
 def test_near_round_visits_each_coefficient_once(NU, NC, seed):
     rng = np.random.default_rng(seed)
