@@ -32,6 +32,7 @@ METRIC = "MOT steps/s and M2L roofline %, chosen vs plain FP64 IFMM at rel err 1
 PEAK_HBM = 8.0e12          # B/s
 PEAK_FP64 = 78.6e12        # FLOP/s, dense FP64 on the matrix cores
 PEAK_FP32 = 157.3e12       # FLOP/s, dense FP32 on the matrix cores
+PEAK_BF16 = 2.5e15         # FLOP/s, dense bf16 on the matrix cores
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_m2l_off_sphere20480_traffic.json")
 NT = 1000                  # steps of the workload
 
@@ -333,7 +334,10 @@ def far_study(torch, tdbem):
         rng = np.random.default_rng(p)
         hist = torch.tensor(rng.standard_normal((n_hist, 3 * len(f) // 2)), device="cuda")
         pots = {}
-        for name, m2l in (("dense", tdbem.M2L_AUTO), ("fft", tdbem.M2L_FFT)):
+        forms = [("dense", tdbem.M2L_AUTO), ("fft", tdbem.M2L_FFT)]
+        if p == 4:
+            forms.append(("bf16", tdbem.M2L_BF16))
+        for name, m2l in forms:
             S = tdbem.Solver(v, f, tdbem.Config(dt=cdt / C0, mode=tdbem.MODE_IFMM, p_s=p, p_t=p, leaf_max=64, m2l=m2l))
             info = S.info()
             o = torch.zeros(S.ne, dtype=torch.float64, device="cuda")
@@ -352,7 +356,7 @@ def far_study(torch, tdbem):
                 for a in range(M, n_hist + 1, M):
                     lags = min(info["windows"][l], a // M)
                     nl += 1
-                    if name == "dense":
+                    if name != "fft":
                         work += info["nilist"][l] * lags * 7 * 2.0 * nn * nn
                     else:
                         work += (info["nilist"][l] * lags * (7 + 2) + info["ncells"][l] * 7) * nf * 16.0
@@ -364,16 +368,20 @@ def far_study(torch, tdbem):
             if name == "dense":
                 r.update({"flop_per_launch": work / max(nl, 1), "achieved_tflops": rate / 1e12,
                           "frac_fp64_mfma": rate / PEAK_FP64})
+            elif name == "bf16":
+                r.update({"flop_per_launch": work / max(nl, 1), "achieved_tflops": rate / 1e12,
+                          "frac_bf16_mfma": rate / PEAK_BF16})
             else:
                 r.update({"bytes_per_launch": work / max(nl, 1), "achieved_gbs": rate / 1e9,
                           "frac_hbm": rate / PEAK_HBM})
             out.append(r)
             S.close()
             torch.cuda.empty_cache()
-        d = float((pots["fft"] - pots["dense"]).abs().max() / pots["dense"].abs().max())
-        out[-1]["rel_diff_vs_dense"] = d
-        print(json.dumps(out[-2]), flush=True)
-        print(json.dumps(out[-1]), flush=True)
+        for r in out[-len(forms):]:
+            if r["m2l"] != "dense":
+                r["rel_diff_vs_dense"] = float((pots[r["m2l"]] - pots["dense"]).abs().max() /
+                                               pots["dense"].abs().max())
+            print(json.dumps(r), flush=True)
     return out
 
 

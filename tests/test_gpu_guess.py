@@ -24,9 +24,9 @@ from paper_2303_05006_amd import tdbem
 from paper_2303_05006_amd.inputs import icosphere, ellipsoid, gaussian_pulse, random_pulses, C0
 
 WEIGHTS = os.path.join(os.path.dirname(tdbem.__file__), "weights", "guess_mlp_icosphere5120.npy")
-# held-out gain the trained network must reach (GMRES iterations per step),
-# below the gain measured with the committed weights
-MIN_GAIN = 0.05
+# held-out gain the trained network must reach (GMRES iterations per step);
+# the committed weights (200 seeded training runs) measured 13.10 -> 12.13
+MIN_GAIN = 0.5
 DT = 0.5e-9
 
 
@@ -309,7 +309,7 @@ def test_trained_guess_reduces_iterations_on_a_held_out_body():
     assert abs(res["zero"] - res["extrap"]) < 0.02
     assert res["learned"] <= res["extrap"] - MIN_GAIN
     assert res["learned"] <= res["zero"] - MIN_GAIN
-    assert used["learned"] >= 200
+    assert used["learned"] >= 700
 
 
 @pytest.mark.parametrize("prec,tol", [(tdbem.FP64, 1e-9), (tdbem.FP32, 1e-5)])
