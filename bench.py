@@ -179,12 +179,24 @@ def cpu_baseline(workload, min_seconds=10.0):
                        f"coefficients and LU factors precomputed, untimed")}
 
 
-def make_solver(torch, tdbem, w, form, guess, rtol):
+NEAR_FORMS = [(2, 1), (1, 1), (3, 1), (2, 2), (1, 2), (2, 0), (1, 0)]   # TDBEM_Q_TUNED shapes of near_kernel 1..7
+
+
+def make_solver(torch, tdbem, w, form, guess, rtol, same_as=None):
+    """A context of the workload; the set-up autotuner picks the near-field
+    form and the solve's blocks, unless same_as (a TDBEM_Q_TUNED record) fixes
+    them to another context's choice."""
     nr = len(w.pulses)
     prec = tdbem.FP64 if form == "fp64" else tdbem.FP32
+    fix = {}
+    if same_as is not None:
+        fix = dict(autotune=0, near_kernel=NEAR_FORMS.index((int(same_as[0]), int(same_as[1]))) + 1,
+                   gmres_blocks=int(same_as[2]))
+    else:
+        fix = dict(autotune=1)
     cfg = tdbem.Config(dt=w.dt, nt=w.nt, theta=w.theta, zeta=w.zeta, leaf_max=w.leaf_max, mode=tdbem.MODE_IFMM,
                        precision=prec, n_rhs=nr, gmres_rtol=rtol, gmres_maxit=60,
-                       guess=tdbem.GUESS_LEARNED if guess == "learned" else tdbem.GUESS_EXTRAP)
+                       guess=tdbem.GUESS_LEARNED if guess == "learned" else tdbem.GUESS_EXTRAP, **fix)
     t0 = time.perf_counter()
     S = tdbem.Solver(w.verts, w.tris, cfg)
     if guess == "learned":
@@ -491,6 +503,7 @@ def main():
 
     S, setup_s = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol)
     info = S.info()
+    tuned = S.query_array(tdbem.Q_TUNED, 4, np.int32)
     ne = S.ne
     # the pulse reaches the sphere (radius 1 m) after its delay minus the light time to the centre
     arrival = int(math.ceil((w.pulses[0].delay - 1.0 / C0) / w.dt))
@@ -536,13 +549,15 @@ def main():
         "setup_s": setup_s,
         "hierarchy": {k: info[k] for k in ("lmax", "Mt", "ncells", "nilist", "near_nnz", "near_pairs", "z0_nnz",
                                            "windows")},
+        "tuned": dict(zip(("near_lag_steps", "near_pair_blocks", "solve_blocks", "autotuned"),
+                          (int(x) for x in tuned))),
         "device_gb": info["device_bytes"] / 1e9,
     }
     S.close()
     if not args.no_compare_loop:
         # the other way of issuing the same timed steps, on a fresh context:
         # K tdbem_step calls (a host wait per step) against one tdbem_march
-        Sx, _ = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol)
+        Sx, _ = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol, same_as=tuned)
         trx = torch.zeros_like(traj) if traj is not None else None
         elx, itx, _ = march(torch, Sx, V, lead, K, lead + K, trx, deferred=args.step_loop)
         Sx.close()
