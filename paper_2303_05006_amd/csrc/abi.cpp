@@ -415,7 +415,6 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     C->d_nl = dupload(C, nl);
     C->d_npair_j = dupload(C, nj);
     C->d_npair_gl = dupload(C, ngl);
-    C->d_coef = d_val;
     C->d_nval = dalloc<double>(C, nnz2);
     if (cfg->precision == TDBEM_FP32) C->d_nval32 = dalloc<float>(C, nnz2);
     if (cfg->precision == TDBEM_BF16) C->d_nval16 = dalloc<unsigned short>(C, nnz2);
@@ -423,7 +422,19 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
         int64_t *d_src = dupload(C, nsrc);
         launch_near_to_jds(C, d_src, d_val, s);
         TD_HIP(hipStreamSynchronize(s));
+        dfree(C, d_src, nsrc.size());
     }
+    // the pair-major coefficients leave the device: a host copy serves
+    // tdbem_near_rows; the other set-up arrays are released
+    C->h_coef.resize(nnz);
+    TD_HIP(hipMemcpy(C->h_coef.data(), d_val, nnz * sizeof(double), hipMemcpyDeviceToHost));
+    dfree(C, d_val, nnz);
+    dfree(C, d_z0idx, z0idx.size());
+    dfree(C, d_off, off.size());
+    dfree(C, d_pi, np);
+    dfree(C, d_pj, np);
+    dfree(C, d_lo, np);
+    dfree(C, d_hi, np);
     C->max_lag = maxlag;
     // keep host copies of the pair structure for inspection
     C->hp_i.swap(pi); C->hp_j.swap(pj); C->hp_lo.swap(glo); C->hp_hi.swap(ghi); C->hp_off.swap(off);
@@ -947,8 +958,7 @@ int tdbem_near_rows(tdbem_ctx *C, const int32_t *rows, int32_t n, int32_t G, dou
     TD_GUARD({
         const int ne = C->ne;
         std::memset(out, 0, sizeof(double) * (size_t)n * ne * G);
-        std::vector<double> val(C->hp_nnz);
-        TD_HIP(hipMemcpy(val.data(), C->d_coef, C->hp_nnz * sizeof(double), hipMemcpyDeviceToHost));
+        const std::vector<double> &val = C->h_coef;
         // row ranges in the (sorted by i) pair list
         for (int r = 0; r < n; ++r) {
             TD_REQUIRE(rows[r] >= 0 && rows[r] < ne, TDBEM_EINVAL, "row out of range");

@@ -157,7 +157,7 @@ struct tdbem_ctx {
     double *d_nval = nullptr;       // [nnz] FP64 values
     float *d_nval32 = nullptr;      // [nnz] FP32 copy (FP32 form)
     void *d_nval16 = nullptr;       // [nnz] bf16 copy (BF16 form)
-    double *d_coef = nullptr;       // pair-major coefficients of every pair (all lags), for inspection
+    std::vector<double> h_coef;     // pair-major coefficients of every pair (all lags), host copy for inspection
     int max_lag = 0;
 
     // Z0 = Zt^(1) CSR (leaf order)
@@ -222,6 +222,19 @@ inline T *dalloc(tdbem_ctx *C, size_t n) {
     C->allocs.push_back(p);
     C->dev_bytes += n * sizeof(T);
     return (T *)p;
+}
+// release a set-up temporary allocated with dalloc before the context ends
+template <typename T>
+inline void dfree(tdbem_ctx *C, T *&p, size_t n) {
+    if (!p) return;
+    for (size_t i = 0; i < C->allocs.size(); ++i)
+        if (C->allocs[i] == (void *)p) {
+            C->allocs.erase(C->allocs.begin() + i);
+            break;
+        }
+    TD_HIP(hipFree(p));
+    C->dev_bytes -= std::max<size_t>(n, 1) * sizeof(T);
+    p = nullptr;
 }
 template <typename T>
 inline T *dupload(tdbem_ctx *C, const std::vector<T> &v) {
