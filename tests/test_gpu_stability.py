@@ -61,3 +61,37 @@ def test_sphere5120_march_1200_steps_decays(mode):
     S = tdbem.Solver(v, f, tdbem.Config(dt=0.02 / C0, nt=1200, mode=mode, gmres_rtol=1e-12, gmres_maxit=200))
     _check(f"sphere5120 mode {mode}", _window_norms(S, [gaussian_pulse(300e6, 200e6)], 1200, 100, torch))
     S.close()
+
+
+@pytest.mark.parametrize("name,kw,trips", [
+    ("split, CHI-FD (the paper's form)", {}, False),
+    ("d2U/dt2 on the kernel", dict(dt2=tdbem.DT2_KERNEL), True),
+    ("CFIE3", dict(cfie=tdbem.CFIE3), True),
+    ("Lagrange in time", dict(interp=tdbem.INTERP_LAGRANGE), True)])
+def test_fast6_late_time_monitor(name, kw, trips):
+    """FAST6 (p = 6, widened boxes, Fourier-domain M2L) on the 5120-triangle
+    sphere, c dt = 0.02 m, 1500 steps, growth_limit 10 (Section 4.3): the
+    variants the paper reports unstable (the second time derivative on the
+    kernel, CFIE3) and the Lagrange temporal interpolant grow after the pulse
+    and trip the monitor (measured at steps 1024, 788 and 510); the paper's
+    form (CHI-FD, derivatives split between kernel and interpolant) stays
+    well within the limit (below 3e-3 of its peak from step 500 on)."""
+    torch = _torch()
+    v, f = icosphere(4)
+    nt = 1500
+    S = tdbem.Solver(v, f, tdbem.Config(dt=0.02 / C0, nt=nt, mode=tdbem.MODE_IFMM, p_s=6, p_t=6, box_widen=1,
+                                        m2l=tdbem.M2L_FFT, gmres_rtol=1e-10, gmres_maxit=200, growth_limit=10.0,
+                                        **kw))
+    pulse = gaussian_pulse(300e6, 200e6)
+    V = torch.zeros((nt - 1, 1, S.ne), dtype=torch.float64, device="cuda")
+    for a in range(1, nt):
+        S.incident([pulse], a, V[a - 1])
+    J = torch.zeros_like(V)
+    rc, st = S.march(V, J)
+    S.close()
+    tripped = [k + 1 for k, c in enumerate(st) if c == tdbem.EUNSTABLE]
+    print(f"FAST6, {name}: first EUNSTABLE at step {tripped[0] if tripped else None}")
+    assert all(c in (tdbem.OK, tdbem.EUNSTABLE) for c in st)
+    assert bool(tripped) == trips
+    if trips:
+        assert rc == tdbem.EUNSTABLE and tripped[0] > 300
