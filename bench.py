@@ -179,7 +179,7 @@ def cpu_baseline(workload, min_seconds=10.0):
                        f"coefficients and LU factors precomputed, untimed")}
 
 
-NEAR_FORMS = [(2, 1), (1, 1), (3, 1), (2, 2), (1, 2), (2, 0), (1, 0)]   # TDBEM_Q_TUNED shapes of near_kernel 1..7
+NEAR_FORMS = [(2, 1), (1, 1), (3, 1), (2, 2), (1, 2), (2, 0), (1, 0), (0, 0)]   # TDBEM_Q_TUNED shapes, near_kernel 1..8
 
 
 def make_solver(torch, tdbem, w, form, guess, rtol, same_as=None):
@@ -314,10 +314,12 @@ def batched_runs(torch, tdbem, lead, K, rtol, single_fp64_steps_per_s, deferred=
         for a in range(1, last + 1):
             S.incident(w.pulses, a, V[a - 1])
         traj = torch.zeros((last, nr, S.ne), dtype=torch.float64, device="cuda")
+        tuned = S.query_array(tdbem.Q_TUNED, 4, np.int32)
         el, iters, ph = march(torch, S, V, lead, K, last, traj, deferred=deferred)
         roof, _ = kernel_rooflines(S.info(), ph, lead, K, nr, form == "fp64", form)
         out[key] = {"form": form + (" + learned initial guess" if guess == "learned" else ""),
                     "steps_per_s": K / el, "rhs_steps_per_s": nr * K / el, "ms_per_step": el / K * 1e3,
+                    "near_form": "matrix cores, per leaf" if (int(tuned[0]), int(tuned[1])) == (0, 0) else "row kernel",
                     "gmres_iters_mean": float(np.mean(iters)), "roofline": roof,
                     "phase_ms": {k: v[0] for k, v in ph.items()}, "setup_s": setup}
         trajs[key] = traj

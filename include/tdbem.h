@@ -159,10 +159,13 @@ typedef struct {
                                  blocks per round) and, for one right-hand side with gmres_blocks = 0, the
                                  device solve's blocks per system, and keep the fastest (TDBEM_Q_TUNED);
                                  0: the fixed defaults */
-    int32_t near_kernel;      /* one-rhs near-field kernel: 0 the default (or the autotuner's choice); k >= 1
-                                 forces form k - 1: 0-4 the row kernel with (lag steps, pair blocks) per round
-                                 (2,1) (1,1) (3,1) (2,2) (1,2), 5-6 the per-leaf kernel (the leaf's source
-                                 currents staged in LDS) with 2 or 1 lag steps per round */
+    int32_t near_kernel;      /* near-field kernel: 0 the default (or the autotuner's choice); k >= 1 forces
+                                 form k - 1.  One rhs: 0-4 the row kernel with (lag steps, pair blocks) per
+                                 round (2,1) (1,1) (3,1) (2,2) (1,2), 5-6 the per-leaf kernel (the leaf's
+                                 source currents staged in LDS) with 2 or 1 lag steps per round.  Batched
+                                 rhs (FP64 and FP32 forms): 7, the per-leaf matrix-core form (each leaf's
+                                 coefficients as a dense block over its sources and lag window, multiplied
+                                 by the sources' current window on the matrix cores) */
     /* late-time stability monitor (Section 4.3): 0 disables.  Once the tested
      * incident field of a right-hand side has fallen below 1e-6 of its largest
      * norm so far (the excitation has passed), a step returns TDBEM_EUNSTABLE
@@ -281,8 +284,9 @@ enum {
                                 level 2): the window's oldest ceil(3 / M_t) intervals use differences truncated at
                                 the oldest interval's start */
     TDBEM_Q_TUNED = 22       /* int32 [4]: the near-field form in use (lag steps of 4 lags per round, 64-pair
-                                blocks per round; 0 blocks: the per-leaf kernel), the device solve's blocks per
-                                system (0: automatic) and 1 if the set-up autotuner chose them */
+                                blocks per round; 0 blocks: the per-leaf kernel; 0, 0: the batched
+                                matrix-core form), the device solve's blocks per system (0: automatic) and 1
+                                if the set-up autotuner chose them */
 };
 
 /* Phases timed by tdbem_profile (HIP events on the work stream around each

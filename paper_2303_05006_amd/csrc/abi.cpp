@@ -132,6 +132,16 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
         std::iota(rest.begin(), rest.end(), 0);
     }
     NearLeaves &NL = C->nleaf;
+    NL.nleaves = (int)r0.size();
+    C->h_leaf_r0 = r0;
+    C->h_leaf_r1 = r1;
+    C->h_leaf_ns.resize(r0.size());
+    C->h_leaf_gw.resize(r0.size());
+    for (size_t i = 0; i < r0.size(); ++i) {
+        C->h_leaf_ns[i] = soff[i + 1] - soff[i];
+        C->h_leaf_gw[i] = g[2 * i + 1];
+    }
+    C->leaf_cover = covered == (size_t)C->ne;
     NL.nfit = (int)fit.size();
     NL.nrest = (int)rest.size();
     NL.max_window = std::max<size_t>(maxw, 1);
@@ -143,6 +153,73 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
     NL.d_g = dupload(C, g);
     NL.d_loc = dupload(C, loc);
     NL.d_rest = dupload(C, rest);
+}
+
+void launch_leaf_mm_fill(const tdbem_ctx *C, int64_t np, const int *prow, const int64_t *psrc, const int *row_leaf,
+                         const int64_t *aoff, const int *kpad, const double *val, hipStream_t s);
+
+// Batched right-hand sides: the dense per-leaf coefficient blocks of the
+// matrix-core near field (rows x (sources x window), padded to 4 columns),
+// filled from the pair-major set-up coefficients.  Skipped when the leaves do
+// not partition the rows or the blocks would exceed 32 GB.
+static void build_leaf_mm(tdbem_ctx *C, const std::vector<int> &nrow, const int64_t *d_psrc, const double *d_val) {
+    if (!C->leaf_cover) return;
+    const size_t nl = C->h_leaf_r0.size();
+    std::vector<int64_t> aoff(nl);
+    std::vector<int> kpad(nl), row_leaf(C->ne, 0);
+    int64_t tot = 0;
+    for (size_t i = 0; i < nl; ++i) {
+        const int K = C->h_leaf_ns[i] * C->h_leaf_gw[i];
+        kpad[i] = std::max(4, (K + 3) / 4 * 4);
+        aoff[i] = tot;
+        tot += (int64_t)(C->h_leaf_r1[i] - C->h_leaf_r0[i]) * kpad[i];
+        for (int r = C->h_leaf_r0[i]; r < C->h_leaf_r1[i]; ++r) row_leaf[r] = (int)i;
+    }
+    const size_t vb = C->cfg.precision == TDBEM_FP64 ? sizeof(double) : sizeof(float);
+    if ((double)tot * vb > 32e9) return;
+    std::vector<int> prow(nrow.back());
+    for (int i = 0; i < C->ne; ++i)
+        for (int q = nrow[i]; q < nrow[i + 1]; ++q) prow[q] = i;
+    hipStream_t s = C->stream;
+    if (C->cfg.precision == TDBEM_FP64) {
+        C->d_leafA64 = dalloc<double>(C, tot);
+        TD_HIP(hipMemsetAsync(C->d_leafA64, 0, tot * sizeof(double), s));
+    } else {
+        C->d_leafA32 = dalloc<float>(C, tot);
+        TD_HIP(hipMemsetAsync(C->d_leafA32, 0, tot * sizeof(float), s));
+    }
+    C->d_leaf_aoff = dupload(C, aoff);
+    C->d_leaf_kpad = dupload(C, kpad);
+    int *d_prow = dupload(C, prow);
+    C->d_row_leaf = dupload(C, row_leaf);
+    launch_leaf_mm_fill(C, (int64_t)prow.size(), d_prow, d_psrc, C->d_row_leaf, C->d_leaf_aoff, C->d_leaf_kpad, d_val,
+                        s);
+    TD_HIP(hipStreamSynchronize(s));
+    dfree(C, d_prow, prow.size());
+    // column segments of at most LEAF_KSEG columns, one block each, so that
+    // large leaves do not leave the other CUs idle; partial sums per segment
+    constexpr int LEAF_KSEG = 2048;
+    std::vector<int> seg_leaf, seg_k, leaf_seg(1, 0);
+    std::vector<int64_t> seg_poff;
+    int64_t poff = 0;
+    for (size_t i = 0; i < nl; ++i) {
+        const int nr = C->h_leaf_r1[i] - C->h_leaf_r0[i];
+        for (int k = 0; k < kpad[i]; k += LEAF_KSEG) {
+            seg_leaf.push_back((int)i);
+            seg_k.push_back(k);
+            seg_k.push_back(std::min(kpad[i], k + LEAF_KSEG));
+            seg_poff.push_back(poff);
+            poff += (int64_t)nr * C->nrhs;
+        }
+        leaf_seg.push_back((int)seg_leaf.size());
+    }
+    C->leaf_nseg = (int)seg_leaf.size();
+    C->d_seg_leaf = dupload(C, seg_leaf);
+    C->d_seg_k = dupload(C, seg_k);
+    C->d_seg_poff = dupload(C, seg_poff);
+    C->d_leaf_seg = dupload(C, leaf_seg);
+    C->d_leaf_part = dalloc<double>(C, (size_t)std::max<int64_t>(poff, 1));
+    C->leaf_mm_ready = true;
 }
 
 // Set-up autotuner: times the candidates on the context's own data and keeps
@@ -178,6 +255,14 @@ static void autotune(tdbem_ctx *C) {
             if (t < tbest) { tbest = t; best = v; }
         }
         C->near_variant = best;
+    }
+    if (C->nrhs > 1 && C->leaf_mm_ready) {
+        // batched: the row kernel against the per-leaf matrix-core form
+        C->near_variant = 0;
+        const float t_row = time_launches(s, 1, 3, [&] { launch_near(C, C->ring, C->d_tmp, 1.0, s); });
+        C->near_variant = near_variants();
+        const float t_mm = time_launches(s, 1, 3, [&] { launch_near(C, C->ring, C->d_tmp, 1.0, s); });
+        C->near_variant = t_mm < t_row ? near_variants() : 0;
     }
     if (C->nrhs == 1 && C->use_coop && C->cfg.gmres_blocks == 0) {
         const int cand[] = {0, 64, 96, 128, 160, 192, 256};
@@ -278,8 +363,13 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->solver == TDBEM_SOLVER_DEVICE || cfg->solver == TDBEM_SOLVER_HOST, TDBEM_EINVAL, "unknown solver");
     TD_REQUIRE(cfg->gmres_blocks >= 0 && cfg->gmres_blocks <= 256, TDBEM_EINVAL, "gmres_blocks must be in 0..256");
     TD_REQUIRE(cfg->autotune == 0 || cfg->autotune == 1, TDBEM_EINVAL, "autotune must be 0 or 1");
-    TD_REQUIRE(cfg->near_kernel >= 0 && cfg->near_kernel <= near_variants(), TDBEM_EINVAL,
-               "near_kernel must be 0 (default or tuned) or 1.." + std::to_string(near_variants()));
+    TD_REQUIRE(cfg->near_kernel >= 0 && cfg->near_kernel <= near_variants() + 1, TDBEM_EINVAL,
+               "near_kernel must be 0 (default or tuned) or 1.." + std::to_string(near_variants() + 1));
+    TD_REQUIRE(cfg->near_kernel == 0 || (cfg->near_kernel <= near_variants()) == (cfg->n_rhs == 1), TDBEM_EINVAL,
+               "near_kernel 1.." + std::to_string(near_variants()) + " are one-rhs forms, " +
+                   std::to_string(near_variants() + 1) + " the batched form");
+    TD_REQUIRE(cfg->near_kernel != near_variants() + 1 || cfg->precision != TDBEM_BF16, TDBEM_EINVAL,
+               "the batched matrix-core near field is built for the FP64 and FP32 forms");
     TD_REQUIRE(cfg->near_kernel == 0 || cfg->autotune == 0, TDBEM_EINVAL, "near_kernel and autotune exclude each other");
     TD_REQUIRE(cfg->growth_limit >= 0.0, TDBEM_EINVAL, "growth_limit must be non-negative");
     TD_REQUIRE(cfg->guess == TDBEM_GUESS_EXTRAP || cfg->guess == TDBEM_GUESS_LEARNED, TDBEM_EINVAL, "unknown guess");
@@ -407,7 +497,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
             for (int l = 0; l < len; ++l) nl[(size_t)i * L + l]++;
         }
     C->near_L = std::max(L, 1);
-    if (C->nrhs == 1) build_near_leaves(C, nrow, nj, ngl);
+    build_near_leaves(C, nrow, nj, ngl);
     C->near_pairs = (int64_t)nj.size();
     C->near_nnz = nnz2;
     C->d_nrow_ptr = dupload(C, nrow);
@@ -421,6 +511,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     {
         int64_t *d_src = dupload(C, nsrc);
         launch_near_to_jds(C, d_src, d_val, s);
+        if (C->nrhs > 1 && cfg->precision != TDBEM_BF16) build_leaf_mm(C, nrow, d_src, d_val);
         TD_HIP(hipStreamSynchronize(s));
         dfree(C, d_src, nsrc.size());
     }
@@ -471,6 +562,8 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     if (C->d_Jring32) TD_HIP(hipMemsetAsync(C->d_Jring32, 0, (size_t)ne * R * C->nrhs * sizeof(float), s));
     TD_HIP(hipStreamSynchronize(s));
     if (cfg->near_kernel > 0) C->near_variant = cfg->near_kernel - 1;
+    TD_REQUIRE(C->near_variant != near_variants() || C->leaf_mm_ready, TDBEM_EINVAL,
+               "the batched matrix-core near field could not be built (leaves or memory)");
     if (cfg->autotune) {
         autotune(C);
         TD_HIP(hipStreamSynchronize(s));

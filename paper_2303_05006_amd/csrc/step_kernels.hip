@@ -9,6 +9,7 @@
 
 #include <cstdio>
 
+#include "mfma.h"
 #include "tdbem_internal.h"
 
 namespace tdbem {
@@ -255,6 +256,144 @@ __global__ void __launch_bounds__(256) k_near_rows_listed(int nrows, const int *
     if (lane == 0) out[row] = acc;
 }
 
+// Batched right-hand sides on the matrix cores, per leaf: the leaf's rows
+// pair with the same sources, so its coefficients form a dense block
+// A_L [rows][K_L], column k = (source s, lag gmin + w) with k = s gw + w (zero
+// where a pair's strip does not reach), and the history sum is the product
+// A_L J_L, J_L [K_L][rhs] the sources' currents at those lags, read from the
+// ring ([edge][slot][rhs]: 16 consecutive rhs of one (source, lag) per k).
+// One block of 4 wavefronts per (leaf, 64 rhs); wavefront w owns rhs
+// 16 w .. 16 w + 15 and the rows in groups of 64 (4 row blocks of 16).
+template <typename T>
+__global__ void __launch_bounds__(256) k_near_leaf_mm(const int *__restrict__ seg_leaf, const int *__restrict__ seg_k,
+                                                      const int64_t *__restrict__ seg_poff,
+                                                      const int *__restrict__ leaf_r0, const int *__restrict__ leaf_r1,
+                                                      const int *__restrict__ leaf_soff, const int *__restrict__ leaf_src,
+                                                      const int *__restrict__ leaf_g, const int64_t *__restrict__ aoff,
+                                                      const int *__restrict__ kpad, const T *__restrict__ A,
+                                                      const T *__restrict__ ring, int ring_mask, int nrhs, int alpha,
+                                                      double *__restrict__ part) {
+    // one block per (segment of a leaf's columns, 64 rhs): chunks of KC
+    // columns of A (64 rows) and KC rows of J (64 rhs) staged in LDS with
+    // coalesced loads, the next chunk's loads in flight during this chunk's
+    // products; the segment's partial sums go to part (summed per leaf in a
+    // fixed order by k_near_leaf_sum)
+    constexpr int KC = 32, AS = KC + (sizeof(T) == 8 ? 1 : 2), BS = 64 + (sizeof(T) == 8 ? 1 : 2);
+    __shared__ T As[64][AS];
+    __shared__ T Bs[KC][BS];
+    const int sg = blockIdx.x, lf = seg_leaf[sg];
+    const int kb = seg_k[2 * sg], ke = seg_k[2 * sg + 1];
+    const int nr = leaf_r1[lf] - leaf_r0[lf];
+    const int s0 = leaf_soff[lf];
+    const int gmin = leaf_g[2 * lf], gw = leaf_g[2 * lf + 1];
+    const int K = (leaf_soff[lf + 1] - s0) * gw, KP = kpad[lf];
+    const T *Al = A + aoff[lf];
+    double *P = part + seg_poff[sg];
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int c0 = blockIdx.y * 64;
+    const int R = ring_mask + 1;
+    // staging map: A (64 x KC): thread -> row tid / 4, columns 8 (tid % 4) .. + 7;
+    // J (KC x 64): thread -> k tid / 8, rhs 8 (tid % 8) .. + 7
+    const int ar = tid >> 2, ac = 8 * (tid & 3);
+    const int bk = tid >> 3, bc = 8 * (tid & 7);
+    for (int rg = 0; rg < nr; rg += 64) {
+        typename Mma<T>::acc_t acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) acc[rb] = typename Mma<T>::acc_t{0, 0, 0, 0};
+        T pa[8], pb[8];
+        auto fetch = [&](int k0) {
+            const int row = rg + ar;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = k0 + ac + e;
+                pa[e] = (row < nr && k < ke) ? Al[(size_t)row * KP + k] : (T)0;
+            }
+            const int k = k0 + bk;
+            const T *jr = nullptr;
+            if (k < ke && k < K) {
+                const int sl = k / gw, w = k % gw;
+                jr = ring + ((size_t)leaf_src[s0 + sl] * R + ((alpha - gmin - w) & ring_mask)) * nrhs;
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int c = c0 + bc + e;
+                pb[e] = (jr && c < nrhs) ? jr[c] : (T)0;
+            }
+        };
+        fetch(kb);
+        for (int k0 = kb; k0 < ke; k0 += KC) {
+            __syncthreads();                      // the previous chunk's products are done with As, Bs
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                As[ar][ac + e] = pa[e];
+                Bs[bk][bc + e] = pb[e];
+            }
+            __syncthreads();
+            if (k0 + KC < ke) fetch(k0 + KC);
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                const int kk = 4 * ks + (lane >> 4);
+                const T bv = Bs[kk][16 * wv + (lane & 15)];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) acc[rb] = Mma<T>::op(As[16 * rb + (lane & 15)][kk], bv, acc[rb]);
+            }
+        }
+        const int col = c0 + 16 * wv + (lane & 15);
+        if (col < nrhs) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = rg + 16 * rb + Mma<T>::row(lane, v);
+                    if (row < nr) P[(size_t)row * nrhs + col] = (double)acc[rb][v];
+                }
+        }
+    }
+}
+
+// out[row][rhs] = sum over the leaf's column segments, in segment order
+__global__ void k_near_leaf_sum(int ne, int nrhs, const int *__restrict__ row_leaf, const int *__restrict__ leaf_r0,
+                                const int *__restrict__ leaf_seg, const int64_t *__restrict__ seg_poff,
+                                const double *__restrict__ part, double *__restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ne * nrhs) return;
+    const int row = (int)(t / nrhs), col = (int)(t % nrhs);
+    const int lf = row_leaf[row], lr = row - leaf_r0[lf];
+    double s = 0.0;
+    for (int sg = leaf_seg[lf]; sg < leaf_seg[lf + 1]; ++sg) s += part[seg_poff[sg] + (size_t)lr * nrhs + col];
+    out[t] = s;
+}
+
+// the dense leaf blocks from the pair-major coefficients: one thread per
+// pair, its strip written at (row, source index gw + lag - gmin)
+template <typename T>
+__global__ void k_leaf_mm_fill(int64_t np, const int *__restrict__ prow, const int *__restrict__ ploc,
+                               const int *__restrict__ pgl, const int64_t *__restrict__ psrc,
+                               const int *__restrict__ row_leaf, const int *__restrict__ leaf_r0,
+                               const int *__restrict__ leaf_g, const int64_t *__restrict__ aoff,
+                               const int *__restrict__ kpad, const double *__restrict__ val, T *__restrict__ A) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= np) return;
+    const int row = prow[q], lf = row_leaf[row];
+    const int g0 = pgl[q] & 0xffff, len = pgl[q] >> 16;
+    const int gmin = leaf_g[2 * lf], gw = leaf_g[2 * lf + 1];
+    T *a = A + aoff[lf] + (size_t)(row - leaf_r0[lf]) * kpad[lf] + (size_t)ploc[q] * gw + (g0 - gmin);
+    for (int l = 0; l < len; ++l) a[l] = (T)val[psrc[q] + l];
+}
+
+void launch_leaf_mm_fill(const tdbem_ctx *C, int64_t np, const int *prow, const int64_t *psrc, const int *row_leaf,
+                         const int64_t *aoff, const int *kpad, const double *val, hipStream_t s) {
+    const NearLeaves &NL = C->nleaf;
+    const unsigned nb = (unsigned)((np + 255) / 256);
+    if (C->d_leafA64)
+        hipLaunchKernelGGL(k_leaf_mm_fill<double>, dim3(nb), dim3(256), 0, s, np, prow, NL.d_loc, C->d_npair_gl, psrc,
+                           row_leaf, NL.d_r0, NL.d_g, aoff, kpad, val, C->d_leafA64);
+    if (C->d_leafA32)
+        hipLaunchKernelGGL(k_leaf_mm_fill<float>, dim3(nb), dim3(256), 0, s, np, prow, NL.d_loc, C->d_npair_gl, psrc,
+                           row_leaf, NL.d_r0, NL.d_g, aoff, kpad, val, C->d_leafA32);
+    TD_HIP(hipGetLastError());
+}
+
 // batched right-hand sides: one wavefront per (row, group of 64 rhs); lanes are rhs
 template <typename VT, typename JT>
 __global__ void __launch_bounds__(256) k_near_jdsN(int ne, int nrhs, const int *__restrict__ row_ptr,
@@ -321,11 +460,16 @@ void launch_near_to_jds(const tdbem_ctx *C, const int64_t *src_off, const double
 // per round; variant 0 is the default (NEAR_NU, NEAR_NC); variants 5 and 6
 // are the per-leaf form with 2 and 1 lag steps (pair blocks reported as 0)
 static constexpr int NEAR_NVAR = 7;
+static constexpr int NEAR_LEAF_MM = 7;    // batched rhs: the per-leaf matrix-core form (near_kernel 8)
 static const int near_var_nu[NEAR_NVAR] = {NEAR_NU, 1, 3, 2, 1, 2, 1};
 static const int near_var_nc[NEAR_NVAR] = {NEAR_NC, 1, 1, 2, 2, 0, 0};
 int near_variants() { return NEAR_NVAR; }
 size_t near_leaf_lds_budget() { return NEAR_LEAF_LDS; }
-void near_variant_shape(int v, int *nu, int *nc) { *nu = near_var_nu[v]; *nc = near_var_nc[v]; }
+void near_variant_shape(int v, int *nu, int *nc) {
+    if (v == NEAR_LEAF_MM) { *nu = 0; *nc = 0; return; }     // the batched matrix-core form
+    *nu = near_var_nu[v];
+    *nc = near_var_nc[v];
+}
 
 template <typename VT, typename JT, int NU, int NC>
 static void launch_jds1(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
@@ -366,6 +510,22 @@ static void launch_near_t(const tdbem_ctx *C, const VT *val, const JT *ring, int
             case 4: launch_jds1<VT, JT, 1, 2>(C, val, ring, alpha, out, s); break;
             default: launch_jds1<VT, JT, NEAR_NU, NEAR_NC>(C, val, ring, alpha, out, s); break;
         }
+    } else if (C->near_variant == NEAR_LEAF_MM && C->leaf_mm_ready) {
+        const NearLeaves &NL = C->nleaf;
+        const dim3 grid((unsigned)C->leaf_nseg, (unsigned)((C->nrhs + 63) / 64));
+        if constexpr (sizeof(JT) == 8)
+            hipLaunchKernelGGL(k_near_leaf_mm<double>, grid, dim3(256), 0, s, C->d_seg_leaf, C->d_seg_k,
+                               C->d_seg_poff, NL.d_r0, NL.d_r1, NL.d_soff, NL.d_src, NL.d_g, C->d_leaf_aoff,
+                               C->d_leaf_kpad, C->d_leafA64, (const double *)ring, C->ring - 1, C->nrhs, alpha,
+                               C->d_leaf_part);
+        else
+            hipLaunchKernelGGL(k_near_leaf_mm<float>, grid, dim3(256), 0, s, C->d_seg_leaf, C->d_seg_k,
+                               C->d_seg_poff, NL.d_r0, NL.d_r1, NL.d_soff, NL.d_src, NL.d_g, C->d_leaf_aoff,
+                               C->d_leaf_kpad, C->d_leafA32, (const float *)ring, C->ring - 1, C->nrhs, alpha,
+                               C->d_leaf_part);
+        const int64_t n = (int64_t)C->ne * C->nrhs;
+        hipLaunchKernelGGL(k_near_leaf_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C->ne, C->nrhs,
+                           C->d_row_leaf, NL.d_r0, C->d_leaf_seg, C->d_seg_poff, C->d_leaf_part, out);
     } else {
         int ngrp = (C->nrhs + 63) / 64;
         unsigned nb = grid8(((int64_t)C->ne * ngrp + 3) / 4);

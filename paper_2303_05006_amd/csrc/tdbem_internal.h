@@ -120,6 +120,7 @@ struct NearLeaves {
     int *d_g = nullptr;             // [leaves][2] first lag and window length
     int *d_loc = nullptr;           // [pairs] source index in the pair's leaf list
     int *d_rest = nullptr;          // [nrest] rows left to the row kernel
+    int nleaves = 0;                // leaves (all of them, for the batched matrix-core form)
 };
 }  // namespace tdbem
 
@@ -183,7 +184,22 @@ struct tdbem_ctx {
     unsigned *d_gbar = nullptr;     // grid-barrier words of the cooperative solve, GMRES_BAR_WORDS per rhs
     int gmres_blocks = 0;           // blocks per system of the cooperative solve (0: automatic)
     int near_variant = 0;           // round shape of the one-rhs near-field kernel (set-up autotuner)
-    tdbem::NearLeaves nleaf;        // the per-leaf near-field form (built for one rhs)
+    tdbem::NearLeaves nleaf;        // per-leaf near-field structure (sources, windows)
+    // batched rhs: dense per-leaf coefficient blocks for the matrix cores
+    bool leaf_mm_ready = false;
+    bool leaf_cover = false;        // the leaves' row ranges partition the rows
+    std::vector<int> h_leaf_r0, h_leaf_r1, h_leaf_ns, h_leaf_gw;   // per leaf: rows, sources, window
+    int64_t *d_leaf_aoff = nullptr; // [leaves] first value of each leaf's block
+    int *d_leaf_kpad = nullptr;     // [leaves] block row length (sources x window, padded to 4)
+    double *d_leafA64 = nullptr;    // FP64 blocks (FP64 form)
+    float *d_leafA32 = nullptr;     // FP32 blocks (FP32 form)
+    int leaf_nseg = 0;              // column segments (a block each) over all leaves
+    int *d_seg_leaf = nullptr;      // [segments] leaf
+    int *d_seg_k = nullptr;         // [segments][2] column range
+    int64_t *d_seg_poff = nullptr;  // [segments] offset of the segment's partial sums [rows][n_rhs]
+    int *d_leaf_seg = nullptr;      // [leaves+1] segment range per leaf
+    int *d_row_leaf = nullptr;      // [ne] leaf of each row
+    double *d_leaf_part = nullptr;  // partial sums of the segments
     bool tuned = false;             // the set-up autotuner chose near_variant / gmres_blocks
     bool use_coop = true;           // device-resident solve
     // late-time stability monitor: per rhs, squared norms of V and J of the

@@ -212,7 +212,7 @@ def test_all_pairs_count_and_config_in_effect():
                                          ("gmres_restart", 33), ("dt2", 3), ("solver", 2), ("growth_limit", -1.0),
                                          ("box_widen", 2), ("p_s", 5), ("p_s", 6), ("m2l", 7),
                                          ("m2l+fp32", tdbem.M2L_FFT), ("m2l+p6", tdbem.M2L_BF16),
-                                         ("near_kernel", 8), ("autotune", 2)])
+                                         ("near_kernel", 8), ("near_kernel", 9), ("autotune", 2)])
 def test_invalid_configuration_fields(field, value):
     """(p_s = 6 with p_t = 4: the orders must agree; the Fourier-domain M2L with
     FP32.)"""
@@ -285,3 +285,30 @@ def test_near_field_forms_agree_bitwise(mode, prec, level):
     ref = outs[0].abs().max()
     for k in range(1, 7):
         assert float((outs[k] - outs[0]).abs().max() / ref) < 1e-13
+
+
+@pytest.mark.parametrize("mode,prec,nr", [(tdbem.MODE_IFMM, tdbem.FP64, 3), (tdbem.MODE_IFMM, tdbem.FP64, 70),
+                                          (tdbem.MODE_IFMM, tdbem.FP32, 3), (tdbem.MODE_DIRECT, tdbem.FP64, 2)])
+def test_batched_near_field_on_the_matrix_cores(mode, prec, nr):
+    """Batched right-hand sides: the per-leaf matrix-core near field
+    (near_kernel 8: each leaf's coefficients as a dense block over its sources
+    and lag window, times the sources' current window) against the row kernel
+    on the same history; 70 rhs spans two groups of 64 with a ragged second.
+    FP64 to rounding of the sums; the FP32 form accumulates in FP32 on the
+    matrix cores (the row kernel in FP64)."""
+    torch = _torch()
+    v, f = icosphere(2)
+    dt = (CDT if mode == tdbem.MODE_IFMM else 0.1) / C0
+    ne = 480
+    hist = torch.tensor(np.random.default_rng(nr).standard_normal((30, nr, ne)), device="cuda")
+    outs = []
+    for k in (0, 8):
+        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=mode, precision=prec, leaf_max=LEAF, n_rhs=nr,
+                                            near_kernel=k))
+        o = torch.zeros((nr, ne), dtype=torch.float64, device="cuda")
+        S.potentials(hist, 30, o)
+        outs.append(o)
+        S.close()
+    rel = float((outs[1] - outs[0]).abs().max() / outs[0].abs().max())
+    print(f"mode {mode}, precision {prec}, {nr} rhs: matrix-core vs row near field {rel:.2e}")
+    assert rel < (1e-12 if prec == tdbem.FP64 else 1e-5)
