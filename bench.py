@@ -255,8 +255,10 @@ def tdbem_codes():
     return {"OK": tdbem.OK}
 
 
-def kernel_rooflines(info, ph, lead, K, nr, prec_fp64, form):
-    """Achieved rates of the M2L and near-field kernels over the timed steps."""
+def kernel_rooflines(info, ph, lead, K, nr, prec_fp64, form, near_mm=False):
+    """Achieved rates of the M2L and near-field kernels over the timed steps.
+    near_mm: the batched near field runs as per-leaf matrix-core products
+    (priced by its algorithmic FLOP, 2 per stored coefficient and rhs)."""
     lmax = info["lmax"]
     gates = gate_schedule(info["Mt"], lmax, lead + 1, lead + K)
     m2l_flops = 0.0
@@ -276,7 +278,12 @@ def kernel_rooflines(info, ph, lead, K, nr, prec_fp64, form):
                           "launches": ph["m2l"][1], "ms_total": ph["m2l"][0],
                           "ms_per_launch": ph["m2l"][0] / max(ph["m2l"][1], 1),
                           "flop_per_launch": m2l_flops / max(ph["m2l"][1], 1)}
-    if t_near > 0:
+    if t_near > 0 and near_mm:
+        near_flops = K * 2.0 * info["near_nnz"] * nr
+        kernels["near"] = {"bound": "mfma", "achieved": near_flops / t_near / 1e12, "unit": "TFLOP/s",
+                           "peak": (PEAK_FP64 if prec_fp64 else PEAK_FP32) / 1e12, "launches": ph["near"][1],
+                           "ms_total": ph["near"][0], "flop_per_launch": near_flops / max(ph["near"][1], 1)}
+    elif t_near > 0:
         kernels["near"] = {"bound": "hbm", "achieved": near_bytes / t_near / 1e9, "unit": "GB/s",
                            "peak": PEAK_HBM / 1e9, "launches": ph["near"][1], "ms_total": ph["near"][0],
                            "bytes_per_launch": near_bytes / max(ph["near"][1], 1)}
@@ -316,11 +323,13 @@ def batched_runs(torch, tdbem, lead, K, rtol, single_fp64_steps_per_s, deferred=
         traj = torch.zeros((last, nr, S.ne), dtype=torch.float64, device="cuda")
         tuned = S.query_array(tdbem.Q_TUNED, 4, np.int32)
         el, iters, ph = march(torch, S, V, lead, K, last, traj, deferred=deferred)
-        roof, _ = kernel_rooflines(S.info(), ph, lead, K, nr, form == "fp64", form)
+        near_mm = (int(tuned[0]), int(tuned[1])) == (0, 0)
+        roof, kern = kernel_rooflines(S.info(), ph, lead, K, nr, form == "fp64", form, near_mm=near_mm)
         out[key] = {"form": form + (" + learned initial guess" if guess == "learned" else ""),
                     "steps_per_s": K / el, "rhs_steps_per_s": nr * K / el, "ms_per_step": el / K * 1e3,
-                    "near_form": "matrix cores, per leaf" if (int(tuned[0]), int(tuned[1])) == (0, 0) else "row kernel",
-                    "gmres_iters_mean": float(np.mean(iters)), "roofline": roof,
+                    "near_form": "matrix cores, per leaf" if near_mm else "row kernel",
+                    "near_leaf_gb": S.info()["near_leaf_bytes"] / 1e9,
+                    "gmres_iters_mean": float(np.mean(iters)), "roofline": roof, "kernels": kern,
                     "phase_ms": {k: v[0] for k, v in ph.items()}, "setup_s": setup}
         trajs[key] = traj
         S.close()

@@ -283,10 +283,13 @@ enum {
     TDBEM_Q_WINDOWS = 21,    /* int32 [l_max+1]: source intervals per M2L per level, mu + ceil(3 / M_t(l)) (0 above
                                 level 2): the window's oldest ceil(3 / M_t) intervals use differences truncated at
                                 the oldest interval's start */
-    TDBEM_Q_TUNED = 22       /* int32 [4]: the near-field form in use (lag steps of 4 lags per round, 64-pair
+    TDBEM_Q_TUNED = 22,      /* int32 [4]: the near-field form in use (lag steps of 4 lags per round, 64-pair
                                 blocks per round; 0 blocks: the per-leaf kernel; 0, 0: the batched
                                 matrix-core form), the device solve's blocks per system (0: automatic) and 1
                                 if the set-up autotuner chose them */
+    TDBEM_Q_NEAR_LEAF_BYTES = 23 /* int64: device bytes of the dense per-leaf near-field blocks of the batched
+                                matrix-core form (0 when they are not built: one rhs, the BF16 form, or over
+                                the 32 GB limit) */
 };
 
 /* Phases timed by tdbem_profile (HIP events on the work stream around each

@@ -181,6 +181,7 @@ static void build_leaf_mm(tdbem_ctx *C, const std::vector<int> &nrow, const int6
     for (int i = 0; i < C->ne; ++i)
         for (int q = nrow[i]; q < nrow[i + 1]; ++q) prow[q] = i;
     hipStream_t s = C->stream;
+    C->leaf_mm_bytes = tot * (int64_t)vb;
     if (C->cfg.precision == TDBEM_FP64) {
         C->d_leafA64 = dalloc<double>(C, tot);
         TD_HIP(hipMemsetAsync(C->d_leafA64, 0, tot * sizeof(double), s));
@@ -1010,6 +1011,7 @@ int tdbem_query(const tdbem_ctx *C, int32_t key, void *out) {
             o[0] = nu; o[1] = nc; o[2] = C->gmres_blocks; o[3] = C->tuned ? 1 : 0;
             break;
         }
+        case TDBEM_Q_NEAR_LEAF_BYTES: *(int64_t *)out = C->leaf_mm_bytes; break;
         case TDBEM_Q_UNSTABLE:
             for (int r = 0; r < C->nrhs; ++r) ((int32_t *)out)[r] = C->mon_trip[r];
             break;

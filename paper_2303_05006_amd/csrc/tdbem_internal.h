@@ -193,6 +193,7 @@ struct tdbem_ctx {
     int *d_leaf_kpad = nullptr;     // [leaves] block row length (sources x window, padded to 4)
     double *d_leafA64 = nullptr;    // FP64 blocks (FP64 form)
     float *d_leafA32 = nullptr;     // FP32 blocks (FP32 form)
+    int64_t leaf_mm_bytes = 0;      // bytes of the dense leaf blocks
     int leaf_nseg = 0;              // column segments (a block each) over all leaves
     int *d_seg_leaf = nullptr;      // [segments] leaf
     int *d_seg_k = nullptr;         // [segments][2] column range

@@ -28,7 +28,7 @@ SOLVER_DEVICE, SOLVER_HOST = 0, 1
 M2L_AUTO, M2L_GENERIC, M2L_FFT, M2L_BF16 = 0, 1, 2, 3
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
     Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT, Q_GUESS_USED, \
-    Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS, Q_TUNED = range(23)
+    Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS, Q_TUNED, Q_NEAR_LEAF_BYTES = range(24)
 PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_march",
@@ -220,7 +220,8 @@ class Solver:
                 "near_nnz": self.query_i64(Q_NEAR_NNZ), "near_pairs": self.query_i64(Q_NEAR_PAIRS),
                 "z0_nnz": self.query_i64(Q_Z0_NNZ), "window": self.query_i32(Q_WINDOW),
                 "windows": self.query_array(Q_WINDOWS, lm + 1, np.int32).tolist(),
-                "device_bytes": self.query_i64(Q_DEVICE_BYTES), "setup_ms": self.query_f64(Q_SETUP_MS)}
+                "device_bytes": self.query_i64(Q_DEVICE_BYTES), "setup_ms": self.query_f64(Q_SETUP_MS),
+                "near_leaf_bytes": self.query_i64(Q_NEAR_LEAF_BYTES)}
 
     # ----------------------------------------------------------------- work
     def incident(self, pulses, step, V):

@@ -287,28 +287,43 @@ def test_near_field_forms_agree_bitwise(mode, prec, level):
         assert float((outs[k] - outs[0]).abs().max() / ref) < 1e-13
 
 
-@pytest.mark.parametrize("mode,prec,nr", [(tdbem.MODE_IFMM, tdbem.FP64, 3), (tdbem.MODE_IFMM, tdbem.FP64, 70),
-                                          (tdbem.MODE_IFMM, tdbem.FP32, 3), (tdbem.MODE_DIRECT, tdbem.FP64, 2)])
-def test_batched_near_field_on_the_matrix_cores(mode, prec, nr):
+@pytest.mark.parametrize("mode,prec,nr,level,cdt", [(tdbem.MODE_IFMM, tdbem.FP64, 3, 2, CDT),
+                                                    (tdbem.MODE_IFMM, tdbem.FP64, 70, 2, CDT),
+                                                    (tdbem.MODE_IFMM, tdbem.FP32, 3, 2, CDT),
+                                                    (tdbem.MODE_DIRECT, tdbem.FP64, 2, 2, 0.1),
+                                                    (tdbem.MODE_IFMM, tdbem.FP64, 5, 3, 0.01)])
+def test_batched_near_field_on_the_matrix_cores(mode, prec, nr, level, cdt):
     """Batched right-hand sides: the per-leaf matrix-core near field
     (near_kernel 8: each leaf's coefficients as a dense block over its sources
     and lag window, times the sources' current window) against the row kernel
     on the same history; 70 rhs spans two groups of 64 with a ragged second.
     FP64 to rounding of the sums; the FP32 form accumulates in FP32 on the
-    matrix cores (the row kernel in FP64)."""
+    matrix cores (the row kernel in FP64).  The last case (1280 triangles,
+    leaves of 64 edges, c dt = 0.01 m, a history as long as the leaves' lag
+    windows) has leaves wider than one column segment of 2048 (source, lag)
+    columns, so their rows sum several segments."""
     torch = _torch()
-    v, f = icosphere(2)
-    dt = (CDT if mode == tdbem.MODE_IFMM else 0.1) / C0
-    ne = 480
-    hist = torch.tensor(np.random.default_rng(nr).standard_normal((30, nr, ne)), device="cuda")
+    v, f = icosphere(level)
+    dt = cdt / C0
+    leaf = LEAF if level == 2 else 64
+    nh = 30 if level == 2 else 160
     outs = []
     for k in (0, 8):
-        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=mode, precision=prec, leaf_max=LEAF, n_rhs=nr,
+        S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=mode, precision=prec, leaf_max=leaf, n_rhs=nr,
                                             near_kernel=k))
+        ne = S.ne
+        if k == 0:
+            hist = torch.tensor(np.random.default_rng(nr).standard_normal((nh, nr, ne)), device="cuda")
         o = torch.zeros((nr, ne), dtype=torch.float64, device="cuda")
-        S.potentials(hist, 30, o)
+        S.potentials(hist, nh, o)
         outs.append(o)
+        lb = S.info()["near_leaf_bytes"]
         S.close()
+    vb = 8 if prec == tdbem.FP64 else 4
+    assert lb > 0
+    if level == 3:
+        assert lb / vb / ne > 2048, "the leaves are expected to span several column segments"
     rel = float((outs[1] - outs[0]).abs().max() / outs[0].abs().max())
-    print(f"mode {mode}, precision {prec}, {nr} rhs: matrix-core vs row near field {rel:.2e}")
+    print(f"mode {mode}, precision {prec}, {nr} rhs, {ne} edges: matrix-core vs row near field {rel:.2e}; "
+          f"leaf blocks {lb / 1e6:.1f} MB")
     assert rel < (1e-12 if prec == tdbem.FP64 else 1e-5)
