@@ -78,17 +78,22 @@ int near_variants();
 void near_variant_shape(int v, int *nu, int *nc);
 
 size_t near_leaf_lds_budget();
+int near_leaf_rows();
 
 // The per-leaf form of the one-rhs near field: per leaf cell, its rows (a
 // range in leaf order), the sorted source edges of its rows' pairs, each
-// pair's index in that list, and the lag window [gmin, gmin + gw) its strips
-// cover.  Leaves whose window exceeds the LDS budget keep the row kernel.
+// pair's index in that list, and per source the lags its strips reach there
+// (the source's part of the leaf's current window; the parts are laid end to
+// end).  Leaves whose window exceeds the LDS budget keep the row kernel; the
+// others are cut into chunks of rows, a block each.  The box window [gmin,
+// gmin + gw) of all strips serves the batched matrix-core form.
 static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const std::vector<int> &nj,
                               const std::vector<int> &ngl) {
     const Tree &T = C->T;
     const size_t jt = C->cfg.precision == TDBEM_FP64 ? sizeof(double) : sizeof(float);
-    const size_t budget = near_leaf_lds_budget() / jt;
-    std::vector<int> r0, r1, soff(1, 0), src, g, loc(nj.size(), 0), fit, rest;
+    const size_t budget = std::min<size_t>(near_leaf_lds_budget() / jt, 65535);
+    const int crow = near_leaf_rows();
+    std::vector<int> r0, r1, soff(1, 0), src, g, loc(nj.size(), 0), pwl(nj.size(), 0), ws, chunk, rest;
     size_t maxw = 0;
     for (int l = 0; l <= T.lmax; ++l) {
         const Level &Lv = T.lev[l];
@@ -110,13 +115,39 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
             const int gw = gmax >= gmin ? gmax - gmin + 1 : 1;
             g.push_back(gmax >= gmin ? gmin : 2);
             g.push_back(gw);
-            for (int q = nrow[a]; q < nrow[b]; ++q)
-                loc[q] = (int)(std::lower_bound(list.begin(), list.end(), nj[q]) - list.begin());
+            std::vector<int> lo(list.size(), 1 << 30), hi(list.size(), -1);
+            for (int q = nrow[a]; q < nrow[b]; ++q) {
+                const int li = (int)(std::lower_bound(list.begin(), list.end(), nj[q]) - list.begin());
+                loc[q] = li;
+                const int g0 = ngl[q] & 0xffff, len = ngl[q] >> 16;
+                if (len > 0) {
+                    lo[li] = std::min(lo[li], g0);
+                    hi[li] = std::max(hi[li], g0 + len - 1);
+                }
+            }
+            std::vector<int> woff(list.size());
+            size_t w = 0;
+            for (size_t k = 0; k < list.size(); ++k) {
+                woff[k] = (int)std::min<size_t>(w, 1 << 30);
+                const int n = hi[k] >= lo[k] ? hi[k] - lo[k] + 1 : 0;
+                ws.push_back(list[k]);
+                ws.push_back(n > 0 ? lo[k] : 0);
+                ws.push_back(woff[k]);
+                ws.push_back(n);
+                w += (size_t)n;
+            }
             src.insert(src.end(), list.begin(), list.end());
             soff.push_back((int)src.size());
-            const size_t w = list.size() * (size_t)gw;
             if (w <= budget) {
-                fit.push_back(id);
+                for (int q = nrow[a]; q < nrow[b]; ++q) {
+                    const int li = loc[q], g0 = ngl[q] & 0xffff, len = ngl[q] >> 16;
+                    pwl[q] = (len > 0 ? woff[li] + g0 - lo[li] : 0) | (len << 16);
+                }
+                for (int r = a; r < b; r += crow) {
+                    chunk.push_back(id);
+                    chunk.push_back(r);
+                    chunk.push_back(std::min(b, r + crow));
+                }
                 maxw = std::max(maxw, w);
             } else {
                 for (int r = a; r < b; ++r) rest.push_back(r);
@@ -127,7 +158,7 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
     size_t covered = 0;
     for (size_t i = 0; i < r0.size(); ++i) covered += (size_t)(r1[i] - r0[i]);
     if (covered != (size_t)C->ne) {
-        fit.clear();
+        chunk.clear();
         rest.resize(C->ne);
         std::iota(rest.begin(), rest.end(), 0);
     }
@@ -142,16 +173,21 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
         C->h_leaf_gw[i] = g[2 * i + 1];
     }
     C->leaf_cover = covered == (size_t)C->ne;
-    NL.nfit = (int)fit.size();
+    NL.nchunk = (int)(chunk.size() / 3);
     NL.nrest = (int)rest.size();
     NL.max_window = std::max<size_t>(maxw, 1);
-    NL.d_fit = dupload(C, fit);
+    if (C->trace)
+        std::fprintf(stderr, "[tdbem] per-leaf near field: %zu leaves, %d chunks of <= %d rows, %d rows left to the "
+                     "row kernel, largest window %zu values\n", r0.size(), NL.nchunk, crow, NL.nrest, maxw);
+    NL.d_chunk = dupload(C, chunk);
     NL.d_r0 = dupload(C, r0);
     NL.d_r1 = dupload(C, r1);
     NL.d_soff = dupload(C, soff);
     NL.d_src = dupload(C, src);
     NL.d_g = dupload(C, g);
     NL.d_loc = dupload(C, loc);
+    NL.d_ws = dupload(C, ws);
+    NL.d_pwl = dupload(C, pwl);
     NL.d_rest = dupload(C, rest);
 }
 
@@ -375,7 +411,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->growth_limit >= 0.0, TDBEM_EINVAL, "growth_limit must be non-negative");
     TD_REQUIRE(cfg->guess == TDBEM_GUESS_EXTRAP || cfg->guess == TDBEM_GUESS_LEARNED, TDBEM_EINVAL, "unknown guess");
     C->stream = (hipStream_t)cfg->stream;
-    if (const char *dbg = std::getenv("TDBEM_DEBUG_GMRES")) C->debug_gmres = dbg[0] == '1';   // trace only
+    if (const char *dbg = std::getenv("TDBEM_TRACE")) C->trace = dbg[0] == '1';   // trace only
     C->use_coop = cfg->solver == TDBEM_SOLVER_DEVICE;
     C->gmres_blocks = cfg->gmres_blocks;
     C->nrhs = cfg->n_rhs;

@@ -64,12 +64,14 @@ __device__ __forceinline__ unsigned xcd_block() {
 }
 static unsigned grid8(uint64_t nb) { return (unsigned)((nb + 7) / 8 * 8); }
 
+// One target row of the one-rhs history sum by a wavefront, the currents
+// gathered from the ring (off: the wavefront's L lag offsets in LDS).
 template <typename VT, typename JT, int NU, int NC>
-__global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
-                                                   const int *__restrict__ nl, int L, const int *__restrict__ pj,
-                                                   const int *__restrict__ pgl, const VT *__restrict__ val,
-                                                   const JT *__restrict__ ring, int ring_mask, int alpha,
-                                                   double *__restrict__ out) {
+__device__ __forceinline__ void near_row_gather(int row, int lane, int *off, const int *__restrict__ row_ptr,
+                                                const int64_t *__restrict__ row_vbase, const int *__restrict__ nl,
+                                                int L, const int *__restrict__ pj, const int *__restrict__ pgl,
+                                                const VT *__restrict__ val, const JT *__restrict__ ring,
+                                                int ring_mask, int alpha, double *__restrict__ out) {
     // One wavefront per target row.  The row's pairs are taken 64 NC at a time
     // (a chunk): lane l loads the metadata of pairs l, l + 64, ... of the
     // chunk, and the next chunk's metadata is loaded while this one is summed,
@@ -81,11 +83,6 @@ __global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, cons
     // strips take further rounds of 4 NU lags (the chunk's first pair is its
     // longest: pairs are sorted by strip length).
     constexpr int CH = 64 * NC, NG = 4 * NC;
-    __shared__ int offs[4][NEAR_LMAX];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = (int)xcd_block() * 4 + wv;
-    if (row >= ne) return;
-    int *off = offs[wv];
     near_offsets(nl + (size_t)row * L, L, lane, off);
     const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
     const VT *v = val + row_vbase[row];
@@ -147,113 +144,150 @@ __global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, cons
     if (lane == 0) out[row] = acc;
 }
 
-// Per-leaf form of the one-rhs history sum: every row of a leaf pairs with the
-// same source edges (the edges of the leaf's near cells), so a block per leaf
-// first stages those sources' current windows (the slots of lags gmin ..
-// gmin + gw - 1 before alpha) in LDS with coalesced ring-row loads, then sums
-// its rows exactly like k_near_jds1 with the currents read from LDS: only the
-// coefficients and the pair metadata stream from HBM.  Pair q's source is
-// loc[q], its index in the leaf's source list.  Leaves whose window does not
-// fit the LDS budget take k_near_jds1 (their rows are listed separately).
-static constexpr int NEAR_LEAF_THREADS = 512;            // 8 wavefronts share one leaf's window
-static constexpr size_t NEAR_LEAF_LDS = 128 * 1024;     // window budget in bytes (one block per CU)
+template <typename VT, typename JT, int NU, int NC>
+__global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, const int *__restrict__ rows,
+                                                   const int *__restrict__ row_ptr, const int64_t *__restrict__ row_vbase,
+                                                   const int *__restrict__ nl, int L, const int *__restrict__ pj,
+                                                   const int *__restrict__ pgl, const VT *__restrict__ val,
+                                                   const JT *__restrict__ ring, int ring_mask, int alpha,
+                                                   double *__restrict__ out) {
+    __shared__ int offs[4][NEAR_LMAX];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int idx = (int)xcd_block() * 4 + wv;
+    if (idx >= ne) return;
+    const int row = rows ? rows[idx] : idx;      // rows: the listed rows only (ne of them)
+    near_row_gather<VT, JT, NU, NC>(row, lane, offs[wv], row_ptr, row_vbase, nl, L, pj, pgl, val, ring, ring_mask,
+                                    alpha, out);
+}
 
-template <typename VT, typename JT, int NU>
-__global__ void __launch_bounds__(NEAR_LEAF_THREADS) k_near_leaf(const int *__restrict__ leaf_id, const int *__restrict__ leaf_r0,
-                                                   const int *__restrict__ leaf_r1, const int *__restrict__ leaf_soff,
-                                                   const int *__restrict__ leaf_src, const int *__restrict__ leaf_g,
-                                                   const int *__restrict__ row_ptr,
-                                                   const int64_t *__restrict__ row_vbase, const int *__restrict__ nl,
-                                                   int L, const int *__restrict__ ploc, const int *__restrict__ pgl,
-                                                   const VT *__restrict__ val, const JT *__restrict__ ring,
-                                                   int ring_mask, int alpha, double *__restrict__ out) {
+// Per-leaf form of the one-rhs history sum: every row of a leaf pairs with the
+// same source edges (the edges of the leaf's near cells), so a block per
+// chunk of a leaf's rows first stages the currents those sources contribute
+// (per source the lags its strips reach in this leaf, laid end to end) in LDS
+// with coalesced ring-row loads, then sums its rows with the currents read
+// from LDS: only the coefficients and one word of metadata per pair stream
+// from HBM.  With no current gather left on the vector memory path, the lanes
+// are 16 pairs x 4 lags with the pairs fastest, so that each quarter of a
+// coefficient load reads 16 consecutive values of one lag (jagged-diagonal
+// layout): whole cache lines.  Pair q's strip starts at window offset
+// pwl & 0xffff and has pwl >> 16 lags.  Leaves whose window does not fit the
+// LDS budget take the row kernel's gathers, in the first blocks of the same
+// launch (their rows are listed separately).
+static constexpr int NEAR_LEAF_THREADS = 512;            // 8 wavefronts share one window
+static constexpr int NEAR_LEAF_ROWS = 16;                // rows per chunk (a block)
+static constexpr size_t NEAR_LEAF_LDS = 64 * 1024;      // window budget in bytes (two blocks per CU)
+
+template <typename VT, typename JT, int NU, int NC>
+__global__ void __launch_bounds__(NEAR_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_near_leaf(const int *__restrict__ chunk,
+                                                                 const int *__restrict__ leaf_soff,
+                                                                 const int4 *__restrict__ ws, int wbytes,
+                                                                 const int *__restrict__ row_ptr,
+                                                                 const int64_t *__restrict__ row_vbase,
+                                                                 const int *__restrict__ nl, int L,
+                                                                 const int *__restrict__ pwl, int nrest,
+                                                                 const int *__restrict__ rest,
+                                                                 const int *__restrict__ pj,
+                                                                 const int *__restrict__ pgl,
+                                                                 const VT *__restrict__ val, const JT *__restrict__ ring,
+                                                                 int ring_mask, int alpha, double *__restrict__ out) {
+    // dynamic LDS: the window (wbytes), then each wavefront's L lag offsets.
+    // A round takes NC chunks of 64 pairs and NU lag steps of 4 lags: 4 NC NU
+    // coefficient loads per lane in flight; the next chunks' words are loaded
+    // during this one.
+    constexpr int CH = 64 * NC, NG = 4 * NC;
     extern __shared__ __attribute__((aligned(16))) unsigned char near_lds[];
-    JT *Jw = reinterpret_cast<JT *>(near_lds);
-    __shared__ int offs[NEAR_LEAF_THREADS / 64][NEAR_LMAX];
-    const int lf = leaf_id[blockIdx.x];
-    const int r0 = leaf_r0[lf], r1 = leaf_r1[lf];
+    JT *W = reinterpret_cast<JT *>(near_lds);
+    constexpr int WPB = NEAR_LEAF_THREADS / 64;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int *off = reinterpret_cast<int *>(near_lds + wbytes) + wv * L;
+    // the first blocks take the rows of the leaves whose window does not fit,
+    // a wavefront per row with the currents gathered from the ring (started
+    // first: their gathers take longest)
+    const int nrb = (nrest + WPB - 1) / WPB;
+    if ((int)blockIdx.x < nrb) {
+        const int idx = blockIdx.x * WPB + wv;
+        if (idx < nrest)
+            near_row_gather<VT, JT, NEAR_NU, NEAR_NC>(rest[idx], lane, off, row_ptr, row_vbase, nl, L, pj, pgl, val,
+                                                      ring, ring_mask, alpha, out);
+        return;
+    }
+    const int ck = blockIdx.x - nrb;
+    const int lf = chunk[3 * ck], ra = chunk[3 * ck + 1], rb = chunk[3 * ck + 2];
     const int s0 = leaf_soff[lf], ns = leaf_soff[lf + 1] - s0;
-    const int gmin = leaf_g[2 * lf], gw = leaf_g[2 * lf + 1];
     const int R = ring_mask + 1;
-    // stage: Jw[s][w] = J at slot alpha - gmin - w of source s
-    for (int e = threadIdx.x; e < ns * gw; e += blockDim.x) {
-        const int sl = e / gw, w = e % gw;
-        Jw[e] = ring[(size_t)leaf_src[s0 + sl] * R + ((alpha - gmin - w) & ring_mask)];
+    {
+        // stage: W[o_s + w] = J at slot alpha - a_s - w of source s (ws[s] = edge,
+        // a_s, o_s, n_s); 16 lanes per source, SU sources per lane group with
+        // all their loads in flight together
+        constexpr int SU = 16, NGRP = NEAR_LEAF_THREADS / 16;
+        const int grp = threadIdx.x >> 4, k = threadIdx.x & 15;
+        for (int sb = grp; sb < ns; sb += NGRP * SU) {
+            int4 m[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u) m[u] = sb + NGRP * u < ns ? ws[s0 + sb + NGRP * u] : make_int4(0, 0, 0, 0);
+            JT x[SU];
+#pragma unroll
+            for (int u = 0; u < SU; ++u)
+                x[u] = k < m[u].w ? ring[(size_t)m[u].x * R + ((alpha - m[u].y - k) & ring_mask)] : (JT)0;
+#pragma unroll
+            for (int u = 0; u < SU; ++u) {
+                if (k < m[u].w) W[m[u].z + k] = x[u];
+                for (int w = k + 16; w < m[u].w; w += 16)        // sources reaching over 16 lags
+                    W[m[u].z + w] = ring[(size_t)m[u].x * R + ((alpha - m[u].y - w) & ring_mask)];
+            }
+        }
     }
     __syncthreads();
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int sub = lane & 3, pg = lane >> 2;
-    for (int row = r0 + wv; row < r1; row += NEAR_LEAF_THREADS / 64) {
-        int *off = offs[wv];
+    const int pg = lane & 15, sub = lane >> 4;
+    for (int row = ra + wv; row < rb; row += WPB) {
         near_offsets(nl + (size_t)row * L, L, lane, off);
         const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
         const VT *v = val + row_vbase[row];
         double acc = 0.0;
-        for (int c0 = 0; c0 < np; c0 += 64) {
-            const int p = c0 + lane;
-            const int mloc = p < np ? ploc[pb + p] : 0, mgl = p < np ? pgl[pb + p] : 0;
-            const int cnt = min(64, np - c0);
-            const int lmax = __shfl(mgl, 0, 64) >> 16;
-            int jb[4], len[4];
+        int mw[NC];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
+        for (int h = 0; h < NC; ++h) mw[h] = 64 * h + lane < np ? pwl[pb + 64 * h + lane] : 0;
+        for (int c0 = 0; c0 < np; c0 += CH) {
+            int nw[NC];
+#pragma unroll
+            for (int h = 0; h < NC; ++h) {
+                const int p = c0 + CH + 64 * h + lane;
+                nw[h] = p < np ? pwl[pb + p] : 0;
+            }
+            const int cnt = min(CH, np - c0);
+            const int lmax = __shfl(mw[0], 0, 64) >> 16;
+            int jb[NG], len[NG];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
                 const int q = 16 * g + pg;
-                const int lo = __shfl(mloc, q, 64), gl = __shfl(mgl, q, 64);
-                jb[g] = lo * gw + (gl & 0xffff) - gmin;    // window index of the strip's first lag
-                len[g] = q < cnt ? gl >> 16 : 0;
+                const int w = __shfl(mw[g / 4], q & 63, 64);
+                jb[g] = w & 0xffff;
+                len[g] = q < cnt ? w >> 16 : 0;
             }
             for (int lb = 0; lb < lmax; lb += 4 * NU) {
-                double a[4][NU], x[4][NU];
+                double a[NG][NU], x[NG][NU];
 #pragma unroll
                 for (int t = 0; t < NU; ++t) {
                     const int l = lb + 4 * t + sub;
                     const int ol = l < L ? off[l] : 0;
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) {
+                    for (int g = 0; g < NG; ++g) {
                         const bool ok = l < len[g];
                         a[g][t] = ok ? (double)v[ol + c0 + 16 * g + pg] : 0.0;
-                        x[g][t] = ok ? (double)Jw[jb[g] + l] : 0.0;
+                        x[g][t] = ok ? (double)W[jb[g] + l] : 0.0;
                     }
                 }
 #pragma unroll
                 for (int t = 0; t < NU; ++t)
 #pragma unroll
-                    for (int g = 0; g < 4; ++g) acc += a[g][t] * x[g][t];
+                    for (int g = 0; g < NG; ++g) acc += a[g][t] * x[g][t];
             }
+#pragma unroll
+            for (int h = 0; h < NC; ++h) mw[h] = nw[h];
         }
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
         if (lane == 0) out[row] = acc;
     }
-}
-
-// the rows the per-leaf form leaves to the row kernel: one wavefront per listed row
-template <typename VT, typename JT>
-__global__ void __launch_bounds__(256) k_near_rows_listed(int nrows, const int *__restrict__ rows,
-                                                          const int *__restrict__ row_ptr,
-                                                          const int64_t *__restrict__ row_vbase,
-                                                          const int *__restrict__ nl, int L,
-                                                          const int *__restrict__ pj, const int *__restrict__ pgl,
-                                                          const VT *__restrict__ val, const JT *__restrict__ ring,
-                                                          int ring_mask, int alpha, double *__restrict__ out) {
-    __shared__ int offs[4][NEAR_LMAX];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + wv;
-    if (idx >= nrows) return;
-    const int row = rows[idx];
-    int *off = offs[wv];
-    near_offsets(nl + (size_t)row * L, L, lane, off);
-    const int pb = row_ptr[row], np = row_ptr[row + 1] - pb;
-    const VT *v = val + row_vbase[row];
-    const int R = ring_mask + 1;
-    double acc = 0.0;
-    for (int p = lane; p < np; p += 64) {
-        const int j = pj[pb + p], gl = pgl[pb + p];
-        const int g0 = gl & 0xffff, len = gl >> 16;
-        for (int l = 0; l < len; ++l)
-            acc += (double)v[off[l] + p] * (double)ring[(size_t)j * R + ((alpha - g0 - l) & ring_mask)];
-    }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (lane == 0) out[row] = acc;
 }
 
 // Batched right-hand sides on the matrix cores, per leaf: the leaf's rows
@@ -465,6 +499,7 @@ static const int near_var_nu[NEAR_NVAR] = {NEAR_NU, 1, 3, 2, 1, 2, 1};
 static const int near_var_nc[NEAR_NVAR] = {NEAR_NC, 1, 1, 2, 2, 0, 0};
 int near_variants() { return NEAR_NVAR; }
 size_t near_leaf_lds_budget() { return NEAR_LEAF_LDS; }
+int near_leaf_rows() { return NEAR_LEAF_ROWS; }
 void near_variant_shape(int v, int *nu, int *nc) {
     if (v == NEAR_LEAF_MM) { *nu = 0; *nc = 0; return; }     // the batched matrix-core form
     *nu = near_var_nu[v];
@@ -472,38 +507,41 @@ void near_variant_shape(int v, int *nu, int *nc) {
 }
 
 template <typename VT, typename JT, int NU, int NC>
-static void launch_jds1(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
-    unsigned nb = grid8((C->ne + 3) / 4);
-    hipLaunchKernelGGL((k_near_jds1<VT, JT, NU, NC>), dim3(nb), dim3(256), 0, s, C->ne, C->d_nrow_ptr, C->d_nrow_vbase,
-                       C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
+static void launch_jds1(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s,
+                        int nrows = -1, const int *rows = nullptr) {
+    const int n = rows ? nrows : C->ne;
+    unsigned nb = grid8((n + 3) / 4);
+    hipLaunchKernelGGL((k_near_jds1<VT, JT, NU, NC>), dim3(nb), dim3(256), 0, s, n, rows, C->d_nrow_ptr,
+                       C->d_nrow_vbase, C->d_nl, C->near_L, C->d_npair_j, C->d_npair_gl, val, ring, C->ring - 1, alpha,
+                       out);
 }
 
-template <typename VT, typename JT, int NU>
+template <typename VT, typename JT, int NU, int NC>
 static void launch_leaf(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
     const NearLeaves &NL = C->nleaf;
+    const int wbytes = (int)((NL.max_window * sizeof(JT) + 15) / 16 * 16);
+    const size_t lds = (size_t)wbytes + sizeof(int) * (NEAR_LEAF_THREADS / 64) * (size_t)C->near_L;
     static bool lds_set = false;          // windows above 64 KB need the kernel's LDS limit raised
     if (!lds_set) {
-        TD_HIP(hipFuncSetAttribute((const void *)k_near_leaf<VT, JT, NU>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)NEAR_LEAF_LDS));
+        TD_HIP(hipFuncSetAttribute((const void *)k_near_leaf<VT, JT, NU, NC>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(NEAR_LEAF_LDS + sizeof(int) * (NEAR_LEAF_THREADS / 64) * NEAR_LMAX)));
         lds_set = true;
     }
-    if (NL.nfit > 0)
-        hipLaunchKernelGGL((k_near_leaf<VT, JT, NU>), dim3(NL.nfit), dim3(NEAR_LEAF_THREADS),
-                           NL.max_window * sizeof(JT), s,
-                           NL.d_fit, NL.d_r0, NL.d_r1, NL.d_soff, NL.d_src, NL.d_g, C->d_nrow_ptr, C->d_nrow_vbase,
-                           C->d_nl, C->near_L, NL.d_loc, C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
-    if (NL.nrest > 0)
-        hipLaunchKernelGGL((k_near_rows_listed<VT, JT>), dim3((NL.nrest + 3) / 4), dim3(256), 0, s, NL.nrest,
-                           NL.d_rest, C->d_nrow_ptr, C->d_nrow_vbase, C->d_nl, C->near_L, C->d_npair_j,
-                           C->d_npair_gl, val, ring, C->ring - 1, alpha, out);
+    const int nb = (NL.nrest + NEAR_LEAF_THREADS / 64 - 1) / (NEAR_LEAF_THREADS / 64) + NL.nchunk;
+    if (nb > 0)
+        hipLaunchKernelGGL((k_near_leaf<VT, JT, NU, NC>), dim3(nb), dim3(NEAR_LEAF_THREADS), lds, s, NL.d_chunk,
+                           NL.d_soff, (const int4 *)NL.d_ws, wbytes, C->d_nrow_ptr, C->d_nrow_vbase, C->d_nl,
+                           C->near_L, NL.d_pwl, NL.nrest, NL.d_rest, C->d_npair_j, C->d_npair_gl, val, ring,
+                           C->ring - 1, alpha, out);
 }
 
 template <typename VT, typename JT>
 static void launch_near_t(const tdbem_ctx *C, const VT *val, const JT *ring, int alpha, double *out, hipStream_t s) {
     if (C->nrhs == 1) {
         switch (C->near_variant) {
-            case 5: launch_leaf<VT, JT, 2>(C, val, ring, alpha, out, s); break;
-            case 6: launch_leaf<VT, JT, 1>(C, val, ring, alpha, out, s); break;
+            case 5: launch_leaf<VT, JT, 2, 2>(C, val, ring, alpha, out, s); break;
+            case 6: launch_leaf<VT, JT, 1, 2>(C, val, ring, alpha, out, s); break;
             case 1: launch_jds1<VT, JT, 1, 1>(C, val, ring, alpha, out, s); break;
             case 2: launch_jds1<VT, JT, 3, 1>(C, val, ring, alpha, out, s); break;
             case 3: launch_jds1<VT, JT, 2, 2>(C, val, ring, alpha, out, s); break;
@@ -754,7 +792,7 @@ int gmres_solve(tdbem_ctx *C, const double *b, double *x, double rtol, int maxit
             beta[r] = std::sqrt(beta[r]);
             if (!(beta[r] <= rtol * bn[r] || bn[r] == 0.0)) all = false;
         }
-        if (C->debug_gmres) {
+        if (C->trace) {
             fprintf(stderr, "gmres alpha=%d total=%d:", C->alpha, total);
             for (int r = 0; r < nr; ++r) fprintf(stderr, " %.3e/%.3e", beta[r], bn[r]);
             fprintf(stderr, "\n");

@@ -108,17 +108,20 @@ constexpr int GMRES_BAR_WORDS = 2 * 1024;
 }  // namespace tdbem
 
 namespace tdbem {
-// the per-leaf form of the one-rhs near field: leaves whose sources' current
-// windows fit the LDS budget, their source lists and windows, and the rows
-// of the other leaves
+// the per-leaf form of the one-rhs near field: per leaf, its sources and the
+// lags of theirs its pairs reach (a compressed current window), the chunks of
+// rows of the leaves whose window fits the LDS budget, and the rows of the
+// other leaves
 struct NearLeaves {
-    int nfit = 0, nrest = 0;
+    int nchunk = 0, nrest = 0;
     size_t max_window = 0;          // largest staged window (values)
-    int *d_fit = nullptr;           // [nfit] leaf ids taking the per-leaf kernel
+    int *d_chunk = nullptr;         // [nchunk][3] leaf, first row, end row
     int *d_r0 = nullptr, *d_r1 = nullptr;   // [leaves] row range
     int *d_soff = nullptr, *d_src = nullptr;  // [leaves+1] offsets, source edges (leaf order)
-    int *d_g = nullptr;             // [leaves][2] first lag and window length
+    int *d_g = nullptr;             // [leaves][2] first lag and length of the box window (matrix-core form)
     int *d_loc = nullptr;           // [pairs] source index in the pair's leaf list
+    int *d_ws = nullptr;            // [sources][4] edge, first lag, offset in the leaf's window, lags
+    int *d_pwl = nullptr;           // [pairs] window offset of the strip's first lag | strip length << 16
     int *d_rest = nullptr;          // [nrest] rows left to the row kernel
     int nleaves = 0;                // leaves (all of them, for the batched matrix-core form)
 };
@@ -134,7 +137,7 @@ struct tdbem_ctx {
     int alpha = 1;                  // next step
     int ring = 64;                  // history ring length (power of two)
     int last_iters = 0;
-    bool debug_gmres = false;       // TDBEM_DEBUG_GMRES=1: residuals of every restart cycle on stderr
+    bool trace = false;             // TDBEM_TRACE=1: set-up layout notes and host-solver residuals on stderr
     double setup_ms = 0;
     size_t dev_bytes = 0;
     std::vector<void *> allocs;

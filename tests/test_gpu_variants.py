@@ -258,13 +258,12 @@ def test_autotuned_context_marches_like_the_default(mode):
 @pytest.mark.parametrize("mode,prec,level", [(tdbem.MODE_IFMM, tdbem.FP64, 2), (tdbem.MODE_IFMM, tdbem.FP32, 2),
                                              (tdbem.MODE_DIRECT, tdbem.FP64, 3)])
 def test_near_field_forms_agree_bitwise(mode, prec, level):
-    """Every one-rhs near-field form (near_kernel 1..7) on the same history: the
-    per-leaf kernel (forms 5, 6: the leaf's source currents staged in LDS) sums
-    in the row kernel's order (forms 0, 1 with the same lag steps), so their
-    potentials are bitwise equal; the other round shapes agree to FP64
-    rounding.  In the direct mode every pair is near and the leaves' windows
-    exceed the LDS budget, so the per-leaf forms hand their rows to the row
-    kernel."""
+    """Every one-rhs near-field form (near_kernel 1..7) on the same history
+    agrees with the default row kernel to FP64 rounding (the per-leaf forms 6
+    and 7 read the sources' currents from LDS and give each lane other
+    (pair, lag) terms, so they sum in another order).  In the direct mode every
+    pair is near and the leaves' windows exceed the LDS budget, so the
+    per-leaf forms hand all rows to the default row kernel: bitwise equal."""
     torch = _torch()
     v, f = icosphere(level)
     dt = (CDT if mode == tdbem.MODE_IFMM else 0.075) / C0
@@ -278,10 +277,8 @@ def test_near_field_forms_agree_bitwise(mode, prec, level):
         S.potentials(hist, 40, o)
         outs[k - 1] = o
         S.close()
-    if mode == tdbem.MODE_IFMM:
-        assert torch.equal(outs[5], outs[0]) and torch.equal(outs[6], outs[1])
-    else:                                 # both hand every row to the listed-row kernel
-        assert torch.equal(outs[5], outs[6])
+    if mode == tdbem.MODE_DIRECT:         # both hand every row to the row kernel
+        assert torch.equal(outs[5], outs[0]) and torch.equal(outs[6], outs[0])
     ref = outs[0].abs().max()
     for k in range(1, 7):
         assert float((outs[k] - outs[0]).abs().max() / ref) < 1e-13
