@@ -160,12 +160,15 @@ typedef struct {
                                  device solve's blocks per system, and keep the fastest (TDBEM_Q_TUNED);
                                  0: the fixed defaults */
     int32_t near_kernel;      /* near-field kernel: 0 the default (or the autotuner's choice); k >= 1 forces
-                                 form k - 1.  One rhs: 0-4 the row kernel with (lag steps, pair blocks) per
-                                 round (2,1) (1,1) (3,1) (2,2) (1,2), 5-6 the per-leaf kernel (the leaf's
-                                 source currents staged in LDS) with 2 or 1 lag steps per round.  Batched
-                                 rhs (FP64 and FP32 forms): 7, the per-leaf matrix-core form (each leaf's
-                                 coefficients as a dense block over its sources and lag window, multiplied
-                                 by the sources' current window on the matrix cores) */
+                                 form k - 1.  One rhs: 0-4 the row kernel (each row's source currents
+                                 gathered from the ring) with (lag steps, pair blocks) per round (2,1)
+                                 (1,1) (3,1) (2,2) (1,2); 5-6 the per-leaf kernel (per chunk of a leaf's
+                                 rows, the sources' currents staged in LDS) with 2 or 1 lag steps and 2
+                                 pair blocks per round, the default (form 5) when any leaf's window fits.
+                                 Several rhs: 0 the row kernel (lanes are right-hand sides); 7 the
+                                 per-leaf matrix-core form (each leaf's coefficients as a dense block over
+                                 its sources and lag window, multiplied by the sources' current window on
+                                 the matrix cores; FP64 and FP32 forms), the default when it is built */
     /* late-time stability monitor (Section 4.3): 0 disables.  Once the tested
      * incident field of a right-hand side has fallen below 1e-6 of its largest
      * norm so far (the excitation has passed), a step returns TDBEM_EUNSTABLE

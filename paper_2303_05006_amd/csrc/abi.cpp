@@ -75,9 +75,10 @@ size_t noalloc_need(const tdbem_ctx *C);
 size_t gmres_coop_work_doubles(int ne, int nrhs);
 void launch_fill(int64_t n, double v, double *p, hipStream_t s);
 int near_variants();
+constexpr int NEAR_DEFAULT_LEAF = 5;    // the per-leaf kernel, 2 lag steps x 2 pair blocks per round
 void near_variant_shape(int v, int *nu, int *nc);
 
-size_t near_leaf_lds_budget();
+size_t near_leaf_lds_budget(int L);
 int near_leaf_rows();
 
 // The per-leaf form of the one-rhs near field: per leaf cell, its rows (a
@@ -91,7 +92,7 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
                               const std::vector<int> &ngl) {
     const Tree &T = C->T;
     const size_t jt = C->cfg.precision == TDBEM_FP64 ? sizeof(double) : sizeof(float);
-    const size_t budget = std::min<size_t>(near_leaf_lds_budget() / jt, 65535);
+    const size_t budget = std::min<size_t>(near_leaf_lds_budget(C->near_L) / jt, 65535);
     const int crow = near_leaf_rows();
     std::vector<int> r0, r1, soff(1, 0), src, g, loc(nj.size(), 0), pwl(nj.size(), 0), ws, chunk, rest;
     size_t maxw = 0;
@@ -402,9 +403,11 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->autotune == 0 || cfg->autotune == 1, TDBEM_EINVAL, "autotune must be 0 or 1");
     TD_REQUIRE(cfg->near_kernel >= 0 && cfg->near_kernel <= near_variants() + 1, TDBEM_EINVAL,
                "near_kernel must be 0 (default or tuned) or 1.." + std::to_string(near_variants() + 1));
-    TD_REQUIRE(cfg->near_kernel == 0 || (cfg->near_kernel <= near_variants()) == (cfg->n_rhs == 1), TDBEM_EINVAL,
-               "near_kernel 1.." + std::to_string(near_variants()) + " are one-rhs forms, " +
-                   std::to_string(near_variants() + 1) + " the batched form");
+    TD_REQUIRE(cfg->n_rhs == 1 ? cfg->near_kernel <= near_variants()
+                               : (cfg->near_kernel <= 1 || cfg->near_kernel == near_variants() + 1),
+               TDBEM_EINVAL,
+               "near_kernel 1.." + std::to_string(near_variants()) + " are one-rhs forms; with several rhs 1 is "
+                   "the row kernel and " + std::to_string(near_variants() + 1) + " the matrix-core form");
     TD_REQUIRE(cfg->near_kernel != near_variants() + 1 || cfg->precision != TDBEM_BF16, TDBEM_EINVAL,
                "the batched matrix-core near field is built for the FP64 and FP32 forms");
     TD_REQUIRE(cfg->near_kernel == 0 || cfg->autotune == 0, TDBEM_EINVAL, "near_kernel and autotune exclude each other");
@@ -598,7 +601,14 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_HIP(hipMemsetAsync(C->d_Jring, 0, (size_t)ne * R * C->nrhs * sizeof(double), s));
     if (C->d_Jring32) TD_HIP(hipMemsetAsync(C->d_Jring32, 0, (size_t)ne * R * C->nrhs * sizeof(float), s));
     TD_HIP(hipStreamSynchronize(s));
-    if (cfg->near_kernel > 0) C->near_variant = cfg->near_kernel - 1;
+    // defaults: one rhs the per-leaf kernel where leaves are staged, several
+    // the per-leaf matrix-core form where it was built; otherwise the row kernel
+    if (cfg->near_kernel > 0)
+        C->near_variant = cfg->near_kernel - 1;
+    else if (C->nrhs == 1)
+        C->near_variant = C->nleaf.nchunk > 0 ? NEAR_DEFAULT_LEAF : 0;
+    else
+        C->near_variant = C->leaf_mm_ready ? near_variants() : 0;
     TD_REQUIRE(C->near_variant != near_variants() || C->leaf_mm_ready, TDBEM_EINVAL,
                "the batched matrix-core near field could not be built (leaves or memory)");
     if (cfg->autotune) {

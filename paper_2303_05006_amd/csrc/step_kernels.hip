@@ -7,6 +7,7 @@
 // so one pair's lag strip reads consecutive slots of one edge.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 
 #include "mfma.h"
@@ -173,9 +174,18 @@ __global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, cons
 // pwl & 0xffff and has pwl >> 16 lags.  Leaves whose window does not fit the
 // LDS budget take the row kernel's gathers, in the first blocks of the same
 // launch (their rows are listed separately).
-static constexpr int NEAR_LEAF_THREADS = 512;            // 8 wavefronts share one window
-static constexpr int NEAR_LEAF_ROWS = 16;                // rows per chunk (a block)
-static constexpr size_t NEAR_LEAF_LDS = 64 * 1024;      // window budget in bytes (two blocks per CU)
+#ifndef TDBEM_NEAR_LEAF_THREADS
+#define TDBEM_NEAR_LEAF_THREADS 1024
+#endif
+#ifndef TDBEM_NEAR_LEAF_ROWS
+#define TDBEM_NEAR_LEAF_ROWS 32
+#endif
+#ifndef TDBEM_NEAR_LEAF_KB
+#define TDBEM_NEAR_LEAF_KB 144
+#endif
+static constexpr int NEAR_LEAF_THREADS = TDBEM_NEAR_LEAF_THREADS;        // wavefronts sharing one window x 64
+static constexpr int NEAR_LEAF_ROWS = TDBEM_NEAR_LEAF_ROWS;              // rows per chunk (a block)
+static constexpr size_t NEAR_LEAF_LDS = TDBEM_NEAR_LEAF_KB * 1024;       // window budget in bytes
 
 template <typename VT, typename JT, int NU, int NC>
 __global__ void __launch_bounds__(NEAR_LEAF_THREADS) __attribute__((amdgpu_waves_per_eu(4))) k_near_leaf(const int *__restrict__ chunk,
@@ -227,8 +237,13 @@ __global__ void __launch_bounds__(NEAR_LEAF_THREADS) __attribute__((amdgpu_waves
             for (int u = 0; u < SU; ++u) m[u] = sb + NGRP * u < ns ? ws[s0 + sb + NGRP * u] : make_int4(0, 0, 0, 0);
             JT x[SU];
 #pragma unroll
-            for (int u = 0; u < SU; ++u)
-                x[u] = k < m[u].w ? ring[(size_t)m[u].x * R + ((alpha - m[u].y - k) & ring_mask)] : (JT)0;
+            for (int u = 0; u < SU; ++u) {
+                const JT *q = ring + (size_t)m[u].x * R + ((alpha - m[u].y - k) & ring_mask);
+                if constexpr (sizeof(JT) == 8)
+                    x[u] = k < m[u].w ? *q : (JT)0;
+                else                             // unconditional (in-bounds: edge 0 for an absent source)
+                    x[u] = *q;
+            }
 #pragma unroll
             for (int u = 0; u < SU; ++u) {
                 if (k < m[u].w) W[m[u].z + k] = x[u];
@@ -265,22 +280,51 @@ __global__ void __launch_bounds__(NEAR_LEAF_THREADS) __attribute__((amdgpu_waves
                 len[g] = q < cnt ? w >> 16 : 0;
             }
             for (int lb = 0; lb < lmax; lb += 4 * NU) {
-                double a[NG][NU], x[NG][NU];
+                // all loads of the round first, in the stored types, then the products
+                VT a[NG][NU];
+                JT x[NG][NU];
+                if constexpr (sizeof(VT) == 8) {
+                    // loads under the lane mask: rounds past every strip of a
+                    // group issue none
 #pragma unroll
-                for (int t = 0; t < NU; ++t) {
-                    const int l = lb + 4 * t + sub;
-                    const int ol = l < L ? off[l] : 0;
+                    for (int t = 0; t < NU; ++t) {
+                        const int l = lb + 4 * t + sub;
+                        const int ol = l < L ? off[l] : 0;
 #pragma unroll
-                    for (int g = 0; g < NG; ++g) {
-                        const bool ok = l < len[g];
-                        a[g][t] = ok ? (double)v[ol + c0 + 16 * g + pg] : 0.0;
-                        x[g][t] = ok ? (double)W[jb[g] + l] : 0.0;
+                        for (int g = 0; g < NG; ++g) {
+                            const bool ok = l < len[g];
+                            a[g][t] = ok ? v[ol + c0 + 16 * g + pg] : VT(0.0);
+                            x[g][t] = ok ? W[jb[g] + l] : JT(0.0);
+                        }
                     }
+#pragma unroll
+                    for (int t = 0; t < NU; ++t)
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) acc += (double)a[g][t] * (double)x[g][t];
+                } else {
+                    // values widened after the load: under a lane mask the
+                    // compiler waits for each load before the next, so these
+                    // load unconditionally (in-bounds indexes either way) and
+                    // the terms beyond a strip are zeroed in the products
+#pragma unroll
+                    for (int t = 0; t < NU; ++t) {
+                        const int l = lb + 4 * t + sub;
+                        const int ol = l < L ? off[l] : 0;
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            const bool ok = l < len[g];
+                            a[g][t] = v[ok ? ol + c0 + 16 * g + pg : 0];
+                            x[g][t] = W[ok ? jb[g] + l : 0];
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < NU; ++t)
+#pragma unroll
+                        for (int g = 0; g < NG; ++g) {
+                            const bool ok = lb + 4 * t + sub < len[g];
+                            acc = __builtin_fma(ok ? (double)a[g][t] : 0.0, ok ? (double)x[g][t] : 0.0, acc);
+                        }
                 }
-#pragma unroll
-                for (int t = 0; t < NU; ++t)
-#pragma unroll
-                    for (int g = 0; g < NG; ++g) acc += a[g][t] * x[g][t];
             }
 #pragma unroll
             for (int h = 0; h < NC; ++h) mw[h] = nw[h];
@@ -498,7 +542,12 @@ static constexpr int NEAR_LEAF_MM = 7;    // batched rhs: the per-leaf matrix-co
 static const int near_var_nu[NEAR_NVAR] = {NEAR_NU, 1, 3, 2, 1, 2, 1};
 static const int near_var_nc[NEAR_NVAR] = {NEAR_NC, 1, 1, 2, 2, 0, 0};
 int near_variants() { return NEAR_NVAR; }
-size_t near_leaf_lds_budget() { return NEAR_LEAF_LDS; }
+// window budget of a context whose strips reach L lags: the block's LDS
+// (160 KB on gfx950) holds the window and each wavefront's L lag offsets
+size_t near_leaf_lds_budget(int L) {
+    const size_t offs = sizeof(int) * (NEAR_LEAF_THREADS / 64) * (size_t)L + 16;
+    return std::min(NEAR_LEAF_LDS, (size_t)160 * 1024 - offs);
+}
 int near_leaf_rows() { return NEAR_LEAF_ROWS; }
 void near_variant_shape(int v, int *nu, int *nc) {
     if (v == NEAR_LEAF_MM) { *nu = 0; *nc = 0; return; }     // the batched matrix-core form
@@ -521,12 +570,11 @@ static void launch_leaf(const tdbem_ctx *C, const VT *val, const JT *ring, int a
     const NearLeaves &NL = C->nleaf;
     const int wbytes = (int)((NL.max_window * sizeof(JT) + 15) / 16 * 16);
     const size_t lds = (size_t)wbytes + sizeof(int) * (NEAR_LEAF_THREADS / 64) * (size_t)C->near_L;
-    static bool lds_set = false;          // windows above 64 KB need the kernel's LDS limit raised
-    if (!lds_set) {
+    static size_t lds_set = 0;            // dynamic LDS above 64 KB needs the kernel's limit raised
+    if (lds > lds_set) {
         TD_HIP(hipFuncSetAttribute((const void *)k_near_leaf<VT, JT, NU, NC>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(NEAR_LEAF_LDS + sizeof(int) * (NEAR_LEAF_THREADS / 64) * NEAR_LMAX)));
-        lds_set = true;
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        lds_set = lds;
     }
     const int nb = (NL.nrest + NEAR_LEAF_THREADS / 64 - 1) / (NEAR_LEAF_THREADS / 64) + NL.nchunk;
     if (nb > 0)

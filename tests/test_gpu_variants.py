@@ -231,9 +231,9 @@ def test_invalid_configuration_fields(field, value):
 
 @pytest.mark.parametrize("mode", [tdbem.MODE_DIRECT, tdbem.MODE_IFMM])
 def test_autotuned_context_marches_like_the_default(mode):
-    """autotune = 1 picks a near-field round shape and the device solve's
-    blocks per system by timing them at set-up (TDBEM_Q_TUNED); the march is
-    the same up to the order of FP64 sums."""
+    """autotune = 1 picks a near-field form and the device solve's blocks per
+    system by timing them at set-up (TDBEM_Q_TUNED); the march is the same up
+    to the order of FP64 sums."""
     torch = _torch()
     v, f = icosphere(3)
     dt = 0.05 / C0
@@ -244,7 +244,9 @@ def test_autotuned_context_marches_like_the_default(mode):
     print(f"tuned: near round {tuned[0]} lag steps x {tuned[1]} pair blocks, solve blocks {tuned[2]}")
     assert tuned[3] == 1 and (tuned[0], tuned[1]) in {(2, 1), (1, 1), (3, 1), (2, 2), (1, 2), (2, 0), (1, 0)}
     assert tuned[2] in (0, 64, 96, 128, 160, 192, 256)
-    assert A.query_array(tdbem.Q_TUNED, 4, np.int32).tolist() == [2, 1, 0, 0]
+    # the default: the per-leaf kernel (2 lag steps, shape (2, 0)) where any
+    # leaf's window fits the LDS budget, else the row kernel (2, 1)
+    assert A.query_array(tdbem.Q_TUNED, 4, np.int32).tolist() in ([2, 0, 0, 0], [2, 1, 0, 0])
     pulse = gaussian_pulse(300e6, 200e6)
     Ja = _march(A, [pulse], 80, torch).cpu().numpy()
     Jb = _march(B, [pulse], 80, torch).cpu().numpy()
@@ -255,18 +257,21 @@ def test_autotuned_context_marches_like_the_default(mode):
     B.close()
 
 
-@pytest.mark.parametrize("mode,prec,level", [(tdbem.MODE_IFMM, tdbem.FP64, 2), (tdbem.MODE_IFMM, tdbem.FP32, 2),
-                                             (tdbem.MODE_DIRECT, tdbem.FP64, 3)])
-def test_near_field_forms_agree_bitwise(mode, prec, level):
+@pytest.mark.parametrize("mode,prec,level,cdt", [(tdbem.MODE_IFMM, tdbem.FP64, 2, CDT),
+                                                 (tdbem.MODE_IFMM, tdbem.FP32, 2, CDT),
+                                                 (tdbem.MODE_DIRECT, tdbem.FP64, 3, 0.075),
+                                                 (tdbem.MODE_DIRECT, tdbem.FP64, 3, 0.01)])
+def test_near_field_forms_agree_bitwise(mode, prec, level, cdt):
     """Every one-rhs near-field form (near_kernel 1..7) on the same history
     agrees with the default row kernel to FP64 rounding (the per-leaf forms 6
     and 7 read the sources' currents from LDS and give each lane other
-    (pair, lag) terms, so they sum in another order).  In the direct mode every
-    pair is near and the leaves' windows exceed the LDS budget, so the
-    per-leaf forms hand all rows to the default row kernel: bitwise equal."""
+    (pair, lag) terms, so they sum in another order).  In the direct mode at
+    c dt = 0.01 m every pair is near and each leaf's window (all 1920 sources
+    over some 30 lags) exceeds the LDS budget, so the per-leaf forms hand all
+    rows to the default row kernel's gathers: bitwise equal."""
     torch = _torch()
     v, f = icosphere(level)
-    dt = (CDT if mode == tdbem.MODE_IFMM else 0.075) / C0
+    dt = cdt / C0
     ne = 3 * len(f) // 2
     hist = torch.tensor(np.random.default_rng(9).standard_normal((40, ne)), device="cuda")
     outs = {}
@@ -277,7 +282,7 @@ def test_near_field_forms_agree_bitwise(mode, prec, level):
         S.potentials(hist, 40, o)
         outs[k - 1] = o
         S.close()
-    if mode == tdbem.MODE_DIRECT:         # both hand every row to the row kernel
+    if cdt == 0.01:                       # both hand every row to the row kernel's gathers
         assert torch.equal(outs[5], outs[0]) and torch.equal(outs[6], outs[0])
     ref = outs[0].abs().max()
     for k in range(1, 7):
@@ -305,11 +310,11 @@ def test_batched_near_field_on_the_matrix_cores(mode, prec, nr, level, cdt):
     leaf = LEAF if level == 2 else 64
     nh = 30 if level == 2 else 160
     outs = []
-    for k in (0, 8):
+    for k in (1, 8):                      # the row kernel, the matrix-core form
         S = tdbem.Solver(v, f, tdbem.Config(dt=dt, mode=mode, precision=prec, leaf_max=leaf, n_rhs=nr,
                                             near_kernel=k))
         ne = S.ne
-        if k == 0:
+        if k == 1:
             hist = torch.tensor(np.random.default_rng(nr).standard_normal((nh, nr, ne)), device="cuda")
         o = torch.zeros((nr, ne), dtype=torch.float64, device="cuda")
         S.potentials(hist, nh, o)
