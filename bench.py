@@ -75,6 +75,23 @@ def m2l_traffic(form):
         return None
 
 
+def near_traffic():
+    """HBM bytes per launch of the one-rhs per-leaf near-field kernel (FP64)
+    from the same counter summary, or None when its source has changed."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        for name, k in rec.get("other_kernels", {}).items():
+            if name.startswith("k_near_leaf<double"):
+                with open(os.path.join(ROOT, k["source"]), "rb") as f:
+                    if hashlib.sha256(f.read()).hexdigest() == k["source_sha256"]:
+                        return k["bytes_per_launch"]
+        return None
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def copy_probe(torch, mib=512):
     """One plain device copy of known size (read mib MiB, write mib MiB): the
     reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -255,7 +272,7 @@ def tdbem_codes():
     return {"OK": tdbem.OK}
 
 
-def kernel_rooflines(info, ph, lead, K, nr, prec_fp64, form, near_mm=False):
+def kernel_rooflines(info, ph, lead, K, nr, prec_fp64, form, near_mm=False, near_leaf=False):
     """Achieved rates of the M2L and near-field kernels over the timed steps.
     near_mm: the batched near field runs as per-leaf matrix-core products
     (priced by its algorithmic FLOP, 2 per stored coefficient and rhs)."""
@@ -286,7 +303,8 @@ def kernel_rooflines(info, ph, lead, K, nr, prec_fp64, form, near_mm=False):
     elif t_near > 0:
         kernels["near"] = {"bound": "hbm", "achieved": near_bytes / t_near / 1e9, "unit": "GB/s",
                            "peak": PEAK_HBM / 1e9, "launches": ph["near"][1], "ms_total": ph["near"][0],
-                           "bytes_per_launch": near_bytes / max(ph["near"][1], 1)}
+                           "bytes_per_launch": near_bytes / max(ph["near"][1], 1),
+                           "traffic": near_traffic() if (nr == 1 and prec_fp64 and near_leaf) else None}
     dom = max(kernels, key=lambda k: kernels[k]["ms_total"]) if kernels else None
     roof = None
     if dom:
@@ -527,7 +545,8 @@ def main():
     traj = torch.zeros((last, nr, ne), dtype=torch.float64, device="cuda") if chosen else None
     el, iters, ph = march(torch, S, V, lead, K, last, traj, deferred=not args.step_loop)
     prec_fp64 = args.form == "fp64"
-    roof, kernels = kernel_rooflines(info, ph, lead, K, nr, prec_fp64, args.form)
+    roof, kernels = kernel_rooflines(info, ph, lead, K, nr, prec_fp64, args.form,
+                                     near_leaf=int(tuned[1]) == 0 and int(tuned[0]) > 0)
     d0 = S.d0_nnz()
     res = {
         "metric": METRIC,
