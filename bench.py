@@ -199,7 +199,7 @@ def cpu_baseline(workload, min_seconds=10.0):
 NEAR_FORMS = [(2, 1), (1, 1), (3, 1), (2, 2), (1, 2), (2, 0), (1, 0), (0, 0)]   # TDBEM_Q_TUNED shapes, near_kernel 1..8
 
 
-def make_solver(torch, tdbem, w, form, guess, rtol, same_as=None):
+def make_solver(torch, tdbem, w, form, guess, rtol, same_as=None, graph=0):
     """A context of the workload; the set-up autotuner picks the near-field
     form and the solve's blocks, unless same_as (a TDBEM_Q_TUNED record) fixes
     them to another context's choice."""
@@ -213,7 +213,7 @@ def make_solver(torch, tdbem, w, form, guess, rtol, same_as=None):
         fix = dict(autotune=1)
     cfg = tdbem.Config(dt=w.dt, nt=w.nt, theta=w.theta, zeta=w.zeta, leaf_max=w.leaf_max, mode=tdbem.MODE_IFMM,
                        precision=prec, n_rhs=nr, gmres_rtol=rtol, gmres_maxit=60,
-                       guess=tdbem.GUESS_LEARNED if guess == "learned" else tdbem.GUESS_EXTRAP, **fix)
+                       guess=tdbem.GUESS_LEARNED if guess == "learned" else tdbem.GUESS_EXTRAP, graph=graph, **fix)
     t0 = time.perf_counter()
     S = tdbem.Solver(w.verts, w.tris, cfg)
     if guess == "learned":
@@ -223,7 +223,7 @@ def make_solver(torch, tdbem, w, form, guess, rtol, same_as=None):
     return S, time.perf_counter() - t0
 
 
-def march(torch, S, V, lead, K, last, traj, deferred=False):
+def march(torch, S, V, lead, K, last, traj, deferred=False, profile=True):
     """Untimed steps 1..lead, timed steps lead+1..lead+K, untimed steps up to
     last, on the resident incident fields V [last][rhs][N_e]; traj (or None)
     receives J of every step.  deferred: the timed steps in one tdbem_march
@@ -240,7 +240,7 @@ def march(torch, S, V, lead, K, last, traj, deferred=False):
     for a in range(1, lead + 1):
         run(a)
     torch.cuda.synchronize()
-    S.profile(True)
+    S.profile(profile)
     iters = []
     out = traj[lead:lead + K] if traj is not None else (
         torch.zeros((K,) + tuple(V.shape[1:]), dtype=torch.float64, device="cuda") if deferred else None)
@@ -543,7 +543,13 @@ def main():
     for a in range(1, last + 1):
         S.incident(w.pulses, a, V[a - 1])
     traj = torch.zeros((last, nr, ne), dtype=torch.float64, device="cuda") if chosen else None
-    el, iters, ph = march(torch, S, V, lead, K, last, traj, deferred=not args.step_loop)
+    # the timed steps without phase timing (its events cost about 4% of a step)
+    el, iters, _ = march(torch, S, V, lead, K, last, traj, deferred=not args.step_loop, profile=False)
+    # phase pass: the same steps on a fresh context with the same choices, HIP
+    # events around each phase (the kernel rates and phase times below)
+    Sp, _ = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol, same_as=tuned)
+    elp, _, ph = march(torch, Sp, V, lead, K, lead + K, None, deferred=not args.step_loop)
+    Sp.close()
     prec_fp64 = args.form == "fp64"
     roof, kernels = kernel_rooflines(info, ph, lead, K, nr, prec_fp64, args.form,
                                      near_leaf=int(tuned[1]) == 0 and int(tuned[0]) > 0)
@@ -575,6 +581,9 @@ def main():
         "near_interactions_per_s": info["near_nnz"] * nr * K / el,
         "phase_ms": {k: v[0] for k, v in ph.items()},
         "phase_launches": {k: v[1] for k, v in ph.items()},
+        "phase_pass": {"ms_per_step": elp / K * 1e3,
+                       "how": "the timed steps again on a fresh context with HIP events around each phase; "
+                              "roofline, kernels and phase_ms come from it"},
         "gmres_iters_mean": float(np.mean(iters)),
         "setup_s": setup_s,
         "hierarchy": {k: info[k] for k in ("lmax", "Mt", "ncells", "nilist", "near_nnz", "near_pairs", "z0_nnz",
@@ -589,7 +598,7 @@ def main():
         # K tdbem_step calls (a host wait per step) against one tdbem_march
         Sx, _ = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol, same_as=tuned)
         trx = torch.zeros_like(traj) if traj is not None else None
-        elx, itx, _ = march(torch, Sx, V, lead, K, lead + K, trx, deferred=args.step_loop)
+        elx, itx, _ = march(torch, Sx, V, lead, K, lead + K, trx, deferred=args.step_loop, profile=False)
         Sx.close()
         key = "deferred_march" if args.step_loop else "step_loop"
         res[key] = {"steps_per_s": K / elx, "ms_per_step": elx / K * 1e3,
@@ -598,14 +607,32 @@ def main():
         if traj is not None:
             res[key]["bitwise_equal_currents"] = bool(torch.equal(trx[:lead + K], traj[:lead + K]))
         del trx
+    if not args.no_compare_loop and not args.step_loop:
+        # the same timed steps issued from captured HIP graphs (graph = 1) on a
+        # fresh context, against the plain launches of the run above
+        Sg, _ = make_solver(torch, tdbem, w, args.form, args.guess, args.rtol, same_as=tuned, graph=1)
+        trg = torch.zeros_like(traj) if traj is not None else None
+        elg, _, _ = march(torch, Sg, V, lead, K, lead + K, trg, deferred=True, profile=False)
+        built, refreshed = Sg.query_array(tdbem.Q_GRAPHS, 2, np.int64).tolist()
+        Sg.close()
+        res["graph_march"] = {"steps_per_s": K / elg, "ms_per_step": elg / K * 1e3,
+                              "how": "one tdbem_march call with graph = 1 (plain launches: value)",
+                              "graphs_built": built, "graph_refreshes": refreshed}
+        if traj is not None:
+            res["graph_march"]["bitwise_equal_currents"] = bool(torch.equal(trg[:lead + K], traj[:lead + K]))
+        del trg
     if chosen:
         # chosen form on the same incident fields: FP32 near values and M2L
         # products, learned initial guess; error of its march against FP64's
         # over every step to the end of the workload
         S2, setup2 = make_solver(torch, tdbem, w, "fp32", "learned", args.rtol)
         traj32 = torch.zeros_like(traj)
-        el2, iters2, ph2 = march(torch, S2, V, lead, K, last, traj32, deferred=not args.step_loop)
-        roof2, kernels2 = kernel_rooflines(S2.info(), ph2, lead, K, nr, False, "fp32")
+        el2, iters2, _ = march(torch, S2, V, lead, K, last, traj32, deferred=not args.step_loop, profile=False)
+        tuned2 = S2.query_array(tdbem.Q_TUNED, 4, np.int32)
+        S2p, _ = make_solver(torch, tdbem, w, "fp32", "learned", args.rtol, same_as=tuned2)
+        _, _, ph2 = march(torch, S2p, V, lead, K, lead + K, None, deferred=not args.step_loop)
+        roof2, kernels2 = kernel_rooflines(S2p.info(), ph2, lead, K, nr, False, "fp32")
+        S2p.close()
         dn = ((traj32 - traj) ** 2).sum(dim=(1, 2)).sqrt()
         jn = (traj ** 2).sum(dim=(1, 2)).sqrt()
         res["chosen"] = {"form": "fp32 near values and M2L + learned initial guess", "value": K / el2,

@@ -169,6 +169,13 @@ typedef struct {
                                  per-leaf matrix-core form (each leaf's coefficients as a dense block over
                                  its sources and lag window, multiplied by the sources' current window on
                                  the matrix cores; FP64 and FP32 forms), the default when it is built */
+    int32_t graph;            /* 1: tdbem_march issues each step's kernels before and after the device solve
+                                 as launches of HIP graphs captured from them (one graph for the kernels
+                                 before the solve, one per pattern of far-field levels passing their time
+                                 gate after it; later steps update the captured graphs' arguments).  The
+                                 solve's cooperative launch stays a plain launch between the two.  Only
+                                 with the device solver and while phase timing is off; the results are
+                                 bitwise those of 0, the plain launches */
     /* late-time stability monitor (Section 4.3): 0 disables.  Once the tested
      * incident field of a right-hand side has fallen below 1e-6 of its largest
      * norm so far (the excitation has passed), a step returns TDBEM_EUNSTABLE
@@ -290,9 +297,11 @@ enum {
                                 blocks per round; 0 blocks: the per-leaf kernel; 0, 0: the batched
                                 matrix-core form), the device solve's blocks per system (0: automatic) and 1
                                 if the set-up autotuner chose them */
-    TDBEM_Q_NEAR_LEAF_BYTES = 23 /* int64: device bytes of the dense per-leaf near-field blocks of the batched
+    TDBEM_Q_NEAR_LEAF_BYTES = 23, /* int64: device bytes of the dense per-leaf near-field blocks of the batched
                                 matrix-core form (0 when they are not built: one rhs, the BF16 form, or over
                                 the 32 GB limit) */
+    TDBEM_Q_GRAPHS = 24      /* int64 [2]: executable graphs instantiated and argument refreshes by
+                                tdbem_march with graph = 1 since set-up */
 };
 
 /* Phases timed by tdbem_profile (HIP events on the work stream around each

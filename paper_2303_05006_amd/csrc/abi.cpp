@@ -411,6 +411,9 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     TD_REQUIRE(cfg->near_kernel != near_variants() + 1 || cfg->precision != TDBEM_BF16, TDBEM_EINVAL,
                "the batched matrix-core near field is built for the FP64 and FP32 forms");
     TD_REQUIRE(cfg->near_kernel == 0 || cfg->autotune == 0, TDBEM_EINVAL, "near_kernel and autotune exclude each other");
+    TD_REQUIRE(cfg->graph == 0 || cfg->graph == 1, TDBEM_EINVAL, "graph must be 0 or 1");
+    TD_REQUIRE(cfg->graph == 0 || cfg->solver == TDBEM_SOLVER_DEVICE, TDBEM_EINVAL,
+               "graph needs the device solver");
     TD_REQUIRE(cfg->growth_limit >= 0.0, TDBEM_EINVAL, "growth_limit must be non-negative");
     TD_REQUIRE(cfg->guess == TDBEM_GUESS_EXTRAP || cfg->guess == TDBEM_GUESS_LEARNED, TDBEM_EINVAL, "unknown guess");
     C->stream = (hipStream_t)cfg->stream;
@@ -658,27 +661,50 @@ struct MarchRec {
     int k = 0;
 };
 
+// the kernels of a step before the solve: tested field in, monitor norm,
+// near-field history sum, right-hand side, far field, initial guess
+static void step_pre(tdbem_ctx *C, const double *V, int a, bool monitor, hipStream_t s) {
+    const int64_t nv = (int64_t)C->ne * C->nrhs;
+    {
+        PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
+        launch_gather_in(C, V, C->d_rhs, s);
+        if (monitor) launch_colnorm2(C, C->d_rhs, C->d_stat, 0, s);
+    }
+    { PhaseScope ps(C->prof, TDBEM_PH_NEAR, s); launch_near(C, a, C->d_tmp, 1.0, s); }
+    {
+        PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
+        launch_axpby(nv, -1.0, C->d_tmp, 1.0, C->d_rhs, s);
+        if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_subtract_far(C, a, C->d_rhs, s);
+        launch_extrap(C, a, C->d_x, s);
+        if (guess_active(C)) launch_guess(C, a, s);
+    }
+}
+
+// deferred record of a step's solver status (and monitor norms) on the device
+static void step_rec(tdbem_ctx *C, const int *dflag, MarchRec *rec, bool monitor, hipStream_t s) {
+    const size_t nf = 4 * (size_t)C->nrhs;
+    if (monitor) {
+        launch_colnorm2(C, C->d_x, C->d_stat, 1, s);
+        launch_copy_words(C->d_stat, rec->stat + (size_t)rec->k * 2 * C->nrhs, 4 * (size_t)C->nrhs, s);
+    }
+    launch_copy_words(dflag, rec->flags + (size_t)rec->k * nf, nf, s);
+}
+
+// the kernels of a step after the solve: ring, far field, current out
+static void step_post(tdbem_ctx *C, double *Jout, int a, hipStream_t s) {
+    { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_ring_put(C, (a - 1) & (C->ring - 1), C->d_x, s); }
+    if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_after_solve(C, a, s);
+    if (Jout) { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_scatter_out(C, C->d_x, Jout, s); }
+}
+
 static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, const double *Jgiven,
                      bool noalloc = false, MarchRec *rec = nullptr) {
     hipStream_t s = C->stream;
-    const int64_t nv = (int64_t)C->ne * C->nrhs;
     int a = C->alpha;
     int rc = TDBEM_OK;
     const bool monitor = solve && C->cfg.growth_limit > 0.0;
     if (solve) {
-        {
-            PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
-            launch_gather_in(C, V, C->d_rhs, s);
-            if (monitor) launch_colnorm2(C, C->d_rhs, C->d_stat, 0, s);
-        }
-        { PhaseScope ps(C->prof, TDBEM_PH_NEAR, s); launch_near(C, a, C->d_tmp, 1.0, s); }
-        {
-            PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
-            launch_axpby(nv, -1.0, C->d_tmp, 1.0, C->d_rhs, s);
-            if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_subtract_far(C, a, C->d_rhs, s);
-            launch_extrap(C, a, C->d_x, s);
-            if (guess_active(C)) launch_guess(C, a, s);
-        }
+        step_pre(C, V, a, monitor, s);
         bool ok = true;
         {
             PhaseScope ps(C->prof, TDBEM_PH_GMRES, s);
@@ -690,14 +716,7 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
             TD_REQUIRE(launched || (!noalloc && !rec), TDBEM_EHIP, "the device cannot run the cooperative solve");
             if (launched && rec) {
                 // deferred: keep this step's status on the device, no host wait
-                const size_t nf = 4 * (size_t)C->nrhs;
-                if (monitor) {
-                    launch_colnorm2(C, C->d_x, C->d_stat, 1, s);
-                    TD_HIP(hipMemcpyAsync(rec->stat + (size_t)rec->k * 2 * C->nrhs, C->d_stat,
-                                          2 * C->nrhs * sizeof(double), hipMemcpyDeviceToDevice, s));
-                }
-                TD_HIP(hipMemcpyAsync(rec->flags + (size_t)rec->k * nf, dflag, nf * sizeof(int),
-                                      hipMemcpyDeviceToDevice, s));
+                step_rec(C, dflag, rec, monitor, s);
             } else if (launched) {
                 const size_t nf = 4 * (size_t)C->nrhs;
                 if (monitor) {
@@ -732,11 +751,61 @@ static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, co
     } else {
         launch_gather_in(C, Jgiven, C->d_x, s);
     }
-    { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_ring_put(C, (a - 1) & (C->ring - 1), C->d_x, s); }
-    if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_after_solve(C, a, s);
-    if (Jout) { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_scatter_out(C, C->d_x, Jout, s); }
+    step_post(C, Jout, a, s);
     C->alpha = a + 1;
     return rc;
+}
+
+// Capture fn's launches on the context's capture-only stream into a graph,
+// refresh the executable graph ex with it (its arguments; a new executable
+// when the launches differ), and launch ex on the context's stream.
+static void run_graph(tdbem_ctx *C, hipGraphExec_t &ex, const std::function<void(hipStream_t)> &fn) {
+    hipStream_t cs = C->cap_stream;
+    TD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+        fn(cs);
+    } catch (...) {
+        if (hipStreamEndCapture(cs, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    TD_HIP(hipStreamEndCapture(cs, &g));
+    struct GFree { hipGraph_t g; ~GFree() { if (g) (void)hipGraphDestroy(g); } } gfree{g};
+    if (ex) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult r = hipGraphExecUpdateError;
+        if (hipGraphExecUpdate(ex, g, &bad, &r) == hipSuccess && r == hipGraphExecUpdateSuccess) {
+            ++C->graph_updates;
+        } else {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(ex);
+            ex = nullptr;
+        }
+    }
+    if (!ex) {
+        TD_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+        ++C->graph_builds;
+    }
+    TD_HIP(hipGraphLaunch(ex, C->stream));
+}
+
+// one step of tdbem_march from graphs: the kernels before the solve, the
+// cooperative solve (a plain launch), the status record and the kernels
+// after it (one executable per pattern of far-field levels at their gate)
+static void step_graph(tdbem_ctx *C, const double *V, double *Jout, MarchRec *rec) {
+    const int a = C->alpha;
+    const bool monitor = C->cfg.growth_limit > 0.0;
+    if (!C->cap_stream) TD_HIP(hipStreamCreateWithFlags(&C->cap_stream, hipStreamNonBlocking));
+    run_graph(C, C->g_pre, [&](hipStream_t cs) { step_pre(C, V, a, monitor, cs); });
+    const bool launched = gmres_coop_launch(C, C->d_rhs, C->d_x, C->cfg.gmres_rtol, std::max(1, C->cfg.gmres_maxit),
+                                            C->stream);
+    TD_REQUIRE(launched, TDBEM_EHIP, "the device cannot run the cooperative solve");
+    const uint32_t key = C->cfg.mode == TDBEM_MODE_IFMM ? ifmm_gate_mask(C, a) : 0u;
+    run_graph(C, C->g_post[key], [&](hipStream_t cs) {
+        step_rec(C, C->d_iflag, rec, monitor, cs);
+        step_post(C, Jout, a, cs);
+    });
+    C->alpha = a + 1;
 }
 
 void launch_count_d0(const GeoDev &G, int ne, unsigned long long *count, hipStream_t s);
@@ -968,9 +1037,13 @@ static int march_impl(tdbem_ctx *C, const double *V, double *J, int32_t n_steps,
         MarchRec rec;
         rec.stat = (double *)C->d_march;
         rec.flags = (int *)(rec.stat + (size_t)n_steps * 2 * nr);
+        const bool graphs = C->cfg.graph && !C->prof.on;
         for (int k = 0; k < n_steps; ++k) {
             rec.k = k;
-            step_impl(C, V + k * nv, J + k * nv, true, nullptr, false, &rec);
+            if (graphs)
+                step_graph(C, V + k * nv, J + k * nv, &rec);
+            else
+                step_impl(C, V + k * nv, J + k * nv, true, nullptr, false, &rec);
         }
         std::vector<int> fl((size_t)n_steps * 4 * nr);
         std::vector<double> st((size_t)n_steps * 2 * nr);
@@ -1058,6 +1131,7 @@ int tdbem_query(const tdbem_ctx *C, int32_t key, void *out) {
             break;
         }
         case TDBEM_Q_NEAR_LEAF_BYTES: *(int64_t *)out = C->leaf_mm_bytes; break;
+        case TDBEM_Q_GRAPHS: ((int64_t *)out)[0] = C->graph_builds; ((int64_t *)out)[1] = C->graph_updates; break;
         case TDBEM_Q_UNSTABLE:
             for (int r = 0; r < C->nrhs; ++r) ((int32_t *)out)[r] = C->mon_trip[r];
             break;
@@ -1152,6 +1226,10 @@ int tdbem_guess_adam(float *P, const float *G, float *M, float *V, int32_t t, fl
 
 void tdbem_destroy(tdbem_ctx *C) {
     if (!C) return;
+    if (C->g_pre) (void)hipGraphExecDestroy(C->g_pre);
+    for (auto &kv : C->g_post)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    if (C->cap_stream) (void)hipStreamDestroy(C->cap_stream);
     ifmm_destroy(C);
     guess_destroy(C);
     for (void *p : C->allocs) (void)hipFree(p);

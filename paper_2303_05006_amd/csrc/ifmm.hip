@@ -1002,6 +1002,16 @@ static void after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
     }
 }
 
+// the levels whose time gate step alpha passes (bit l): they alone decide
+// which kernels follow a step's solve
+uint32_t ifmm_gate_mask(const tdbem_ctx *C, int alpha) {
+    const FarState *F = C->far;
+    uint32_t m = 0;
+    for (int l = 2; l <= F->lmax; ++l)
+        if (alpha % F->lev[l].M == 0) m |= 1u << l;
+    return m;
+}
+
 void ifmm_after_solve(tdbem_ctx *C, int alpha, hipStream_t s) {
     switch (C->far->P) {
         case 4: after_solve<4>(C, alpha, s); break;

@@ -649,6 +649,20 @@ __global__ void k_scatter_out(int ne, int nrhs, const int *perm, const double *s
     for (int r = 0; r < nrhs; ++r) dst[(size_t)r * ne + e] = src[(size_t)p * nrhs + r];
 }
 // y = a*x + b*y over n values
+// word copy (a kernel rather than a copy command, so that it can sit in a
+// captured graph like the step's other work)
+__global__ void k_copy_words(size_t n, const uint32_t *__restrict__ src, uint32_t *__restrict__ dst) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+void launch_copy_words(const void *src, void *dst, size_t words, hipStream_t s) {
+    if (words == 0) return;
+    hipLaunchKernelGGL(k_copy_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, words,
+                       (const uint32_t *)src, (uint32_t *)dst);
+    TD_HIP(hipGetLastError());
+}
+
 __global__ void k_fill(int64_t n, double v, double *p) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/tdbem.h"
@@ -181,6 +182,10 @@ struct tdbem_ctx {
     double *d_pulse = nullptr;      // [nrhs][11]
     double *d_tmp = nullptr;        // [ne][nrhs] scratch (canonical order io)
     int *d_iflag = nullptr;         // device solver status per rhs: iterations, converged, barrier timeout
+    hipStream_t cap_stream = nullptr;                   // capture-only stream of the graph march
+    hipGraphExec_t g_pre = nullptr;                     // the kernels before the solve
+    std::map<uint32_t, hipGraphExec_t> g_post;          // after the solve, per pattern of gated levels
+    int64_t graph_builds = 0, graph_updates = 0;        // executables instantiated, argument refreshes
     void *d_march = nullptr;        // deferred step records of tdbem_march (grown on demand)
     size_t march_cap = 0;           // steps the records hold
     int *h_iflag = nullptr;         // pinned host mirror
@@ -272,6 +277,8 @@ void launch_guess(tdbem_ctx *C, int alpha, hipStream_t s);
 int64_t guess_used(tdbem_ctx *C);
 void launch_spmv(const tdbem_ctx *C, const double *x, double *y, hipStream_t s);
 void launch_colnorm2(const tdbem_ctx *C, const double *x, double *out, int slot, hipStream_t s);
+void launch_copy_words(const void *src, void *dst, size_t words, hipStream_t s);
+uint32_t ifmm_gate_mask(const tdbem_ctx *C, int alpha);
 int64_t count_d0_nnz(const tdbem_ctx *C);
 void cfie_weights(const tdbem_config &cfg, double &kd, double &zeta);
 void guess_grad(const float *P, const float *X, const float *Y, int64_t n, float *G, float *loss, hipStream_t s);

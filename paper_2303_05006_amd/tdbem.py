@@ -28,7 +28,7 @@ SOLVER_DEVICE, SOLVER_HOST = 0, 1
 M2L_AUTO, M2L_GENERIC, M2L_FFT, M2L_BF16 = 0, 1, 2, 3
 Q_NE, Q_EDGES, Q_LMAX, Q_MT, Q_NEAR_NNZ, Q_NEAR_PAIRS, Q_Z0_NNZ, Q_NCELLS, Q_NILIST, Q_WINDOW, \
     Q_GMRES_ITERS, Q_DEVICE_BYTES, Q_STEP, Q_EDGE_LEAF, Q_SETUP_MS, Q_PHASE_MS, Q_PHASE_COUNT, Q_GUESS_USED, \
-    Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS, Q_TUNED, Q_NEAR_LEAF_BYTES = range(24)
+    Q_CONFIG, Q_D0_NNZ, Q_UNSTABLE, Q_WINDOWS, Q_TUNED, Q_NEAR_LEAF_BYTES, Q_GRAPHS = range(25)
 PHASES = ["near", "gmres", "p2m", "m2m", "m2l", "l2l", "l2p", "other", "m2l_sum"]
 
 EXPORTS = ["tdbem_setup", "tdbem_incident_planewave", "tdbem_potentials", "tdbem_step", "tdbem_march",
@@ -64,7 +64,7 @@ class _Config(ctypes.Structure):
                 ("mode", ctypes.c_int32), ("precision", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
                 ("gmres_rtol", ctypes.c_double), ("gmres_maxit", ctypes.c_int32), ("gmres_restart", ctypes.c_int32),
                 ("guess", ctypes.c_int32), ("solver", ctypes.c_int32), ("gmres_blocks", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("near_kernel", ctypes.c_int32),
+                ("autotune", ctypes.c_int32), ("near_kernel", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("growth_limit", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
@@ -138,6 +138,7 @@ class Config:
     gmres_blocks: int = 0
     autotune: int = 0
     near_kernel: int = 0
+    graph: int = 0
     growth_limit: float = 0.0
 
 
@@ -178,7 +179,7 @@ class Solver:
                     cfg.p_s, cfg.p_t, cfg.interp, cfg.dt2, cfg.m2l, cfg.leaf_max, cfg.min_level, cfg.mu_window,
                     cfg.box_widen, cfg.causal_guard, cfg.mode, cfg.precision, cfg.n_rhs,
                     cfg.gmres_rtol, cfg.gmres_maxit, cfg.gmres_restart, cfg.guess, cfg.solver, cfg.gmres_blocks,
-                    cfg.autotune, cfg.near_kernel,
+                    cfg.autotune, cfg.near_kernel, cfg.graph,
                     cfg.growth_limit, ctypes.c_void_p(s.cuda_stream))
         h = ctypes.c_void_p()
         _check(L.tdbem_setup(ctypes.byref(m), ctypes.byref(c), ctypes.byref(h)))

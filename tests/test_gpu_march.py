@@ -70,3 +70,44 @@ def test_march_reports_per_step_codes_like_the_step_loop():
     assert tdbem.EUNSTABLE in codes
     first = codes.index(tdbem.EUNSTABLE)
     assert rcs[0 if first < (nt - 1) // 3 else 1] == tdbem.EUNSTABLE
+
+
+@pytest.mark.parametrize("mode,nr,limit", [(tdbem.MODE_IFMM, 1, 0.0), (tdbem.MODE_IFMM, 2, 1e6),
+                                           (tdbem.MODE_DIRECT, 1, 1e6)])
+def test_graph_march_equals_plain_march_bitwise(mode, nr, limit):
+    """graph = 1: each step's kernels before and after the device solve are
+    replays of captured HIP graphs whose arguments are refreshed step by step
+    (one executable before the solve, one per pattern of gated far-field
+    levels after it).  Over 89 steps in two calls (a host wait between them)
+    every step's currents are bitwise those of the plain march, and so are
+    the per-step codes; the executables are built once per pattern and then
+    only refreshed."""
+    torch = _torch()
+    v, f = icosphere(2)
+    cfg = dict(dt=0.078 / C0, mode=mode, leaf_max=6, gmres_rtol=1e-12, gmres_maxit=200, growth_limit=limit)
+    A = tdbem.Solver(v, f, tdbem.Config(**cfg, n_rhs=nr))
+    B = tdbem.Solver(v, f, tdbem.Config(**cfg, n_rhs=nr, graph=1))
+    nt = 90
+    pulses = [gaussian_pulse(150e6 + 30e6 * r, 100e6) for r in range(nr)]
+    V = torch.zeros((nt - 1, nr, A.ne), dtype=torch.float64, device="cuda")
+    for a in range(1, nt):
+        A.incident(pulses, a, V[a - 1])
+    k = (nt - 1) // 3
+    outs, codes = [], []
+    for S in (A, B):
+        J = torch.zeros_like(V)
+        rc1, st1 = S.march(V[:k], J[:k])
+        torch.cuda.synchronize()
+        rc2, st2 = S.march(V[k:], J[k:])
+        torch.cuda.synchronize()
+        outs.append(J)
+        codes.append(list(st1) + list(st2))
+    builds, updates = B.query_array(tdbem.Q_GRAPHS, 2, np.int64).tolist()
+    plain = A.query_array(tdbem.Q_GRAPHS, 2, np.int64).tolist()
+    print(f"graph march: {builds} executables built, {updates} refreshes over {nt - 1} steps")
+    A.close()
+    B.close()
+    assert codes[0] == codes[1] and all(c == tdbem.OK for c in codes[0])
+    assert torch.equal(outs[0], outs[1])
+    assert plain == [0, 0]
+    assert builds + updates == 2 * (nt - 1) and builds <= 12
