@@ -80,6 +80,7 @@ void near_variant_shape(int v, int *nu, int *nc);
 
 size_t near_leaf_lds_budget(int L);
 int near_leaf_rows();
+bool near_leaf_sorted();
 
 // The per-leaf form of the one-rhs near field: per leaf cell, its rows (a
 // range in leaf order), the sorted source edges of its rows' pairs, each
@@ -174,6 +175,21 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
         C->h_leaf_gw[i] = g[2 * i + 1];
     }
     C->leaf_cover = covered == (size_t)C->ne;
+    if (near_leaf_sorted()) {
+        // largest chunks (stored coefficients) first: the last blocks to start
+        // are the small ones, so the CUs finish together
+        std::vector<int64_t> work(chunk.size() / 3, 0);
+        for (size_t c = 0; c < work.size(); ++c)
+            for (int r = chunk[3 * c + 1]; r < chunk[3 * c + 2]; ++r)
+                for (int q = nrow[r]; q < nrow[r + 1]; ++q) work[c] += ngl[q] >> 16;
+        std::vector<int> ord(work.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return work[x] > work[y]; });
+        std::vector<int> sorted(chunk.size());
+        for (size_t c = 0; c < ord.size(); ++c)
+            for (int t = 0; t < 3; ++t) sorted[3 * c + t] = chunk[3 * (size_t)ord[c] + t];
+        chunk.swap(sorted);
+    }
     NL.nchunk = (int)(chunk.size() / 3);
     NL.nrest = (int)rest.size();
     NL.max_window = std::max<size_t>(maxw, 1);

@@ -178,10 +178,13 @@ __global__ void __launch_bounds__(256, NC == 1 ? 6 : 4) k_near_jds1(int ne, cons
 #define TDBEM_NEAR_LEAF_THREADS 1024
 #endif
 #ifndef TDBEM_NEAR_LEAF_ROWS
-#define TDBEM_NEAR_LEAF_ROWS 32
+#define TDBEM_NEAR_LEAF_ROWS 64
 #endif
 #ifndef TDBEM_NEAR_LEAF_KB
 #define TDBEM_NEAR_LEAF_KB 144
+#endif
+#ifndef TDBEM_NEAR_LEAF_SORT
+#define TDBEM_NEAR_LEAF_SORT 1
 #endif
 static constexpr int NEAR_LEAF_THREADS = TDBEM_NEAR_LEAF_THREADS;        // wavefronts sharing one window x 64
 static constexpr int NEAR_LEAF_ROWS = TDBEM_NEAR_LEAF_ROWS;              // rows per chunk (a block)
@@ -549,6 +552,7 @@ size_t near_leaf_lds_budget(int L) {
     return std::min(NEAR_LEAF_LDS, (size_t)160 * 1024 - offs);
 }
 int near_leaf_rows() { return NEAR_LEAF_ROWS; }
+bool near_leaf_sorted() { return TDBEM_NEAR_LEAF_SORT != 0; }
 void near_variant_shape(int v, int *nu, int *nc) {
     if (v == NEAR_LEAF_MM) { *nu = 0; *nc = 0; return; }     // the batched matrix-core form
     *nu = near_var_nu[v];
