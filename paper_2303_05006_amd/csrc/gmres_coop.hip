@@ -286,7 +286,17 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
             } else {
                 if (on_chip) block_spmv_lds(rc, ra, tail, nu, A.ptr, A.col, A.vald, wprev, hscale, w, r0, r1);
                 else block_spmv(A.ptr, A.col, A.vald, wprev, hscale, nullptr, w, r0, r1);
-                for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) A.V[(size_t)k * vs + i] = wprev[i] * hscale;
+            }
+            __syncthreads();
+            // The scaled operator has a unit diagonal, A Dinv = I + E: Arnoldi runs
+            // on E (w = E V_k, the same Krylov space) and the identity returns as
+            // the 1 on the Hessenberg diagonal below.  E V_k has no large part
+            // along V_k, so the Gram-Schmidt pass seldom cancels and the second
+            // (DGKS) pass and its barrier are rarely needed.
+            for (int i = r0 + (int)threadIdx.x; i < r1; i += GM_THREADS) {
+                const double vk = k == 0 ? A.V[i] : wprev[i] * hscale;
+                if (k > 0) A.V[(size_t)k * vs + i] = vk;
+                w[i] -= vk;
             }
             __syncthreads();
             // Gram-Schmidt with the norm in the same reduction: h = V^T w and |w|^2;
@@ -333,7 +343,7 @@ __global__ void __launch_bounds__(GM_THREADS) k_gmres_coop(GmresArgs Ain) {
             // Hessenberg column, rotations (every block, identically)
             if (threadIdx.x == 0) {
                 double hn = sqrt(sc[0]);
-                for (int q = 0; q <= k; ++q) H[q * GM_MAXV + k] = h1[q] + h2[q];
+                for (int q = 0; q <= k; ++q) H[q * GM_MAXV + k] = h1[q] + h2[q] + (q == k ? 1.0 : 0.0);
                 double hk1 = hn;
                 for (int q = 0; q < k; ++q) {
                     double a = H[q * GM_MAXV + k], bb = H[(q + 1) * GM_MAXV + k];
