@@ -574,11 +574,14 @@ static void launch_leaf(const tdbem_ctx *C, const VT *val, const JT *ring, int a
     const NearLeaves &NL = C->nleaf;
     const int wbytes = (int)((NL.max_window * sizeof(JT) + 15) / 16 * 16);
     const size_t lds = (size_t)wbytes + sizeof(int) * (NEAR_LEAF_THREADS / 64) * (size_t)C->near_L;
-    static size_t lds_set = 0;            // dynamic LDS above 64 KB needs the kernel's limit raised
-    if (lds > lds_set) {
+    // dynamic LDS above 64 KB needs the kernel's limit raised, per device
+    static size_t lds_set[64] = {};
+    int dev = 0;
+    TD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64 || lds > lds_set[dev]) {
         TD_HIP(hipFuncSetAttribute((const void *)k_near_leaf<VT, JT, NU, NC>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        lds_set = lds;
+        if (dev >= 0 && dev < 64) lds_set[dev] = lds;
     }
     const int nb = (NL.nrest + NEAR_LEAF_THREADS / 64 - 1) / (NEAR_LEAF_THREADS / 64) + NL.nchunk;
     if (nb > 0)
