@@ -5,6 +5,8 @@ calls and only defers the reading of each step's solver status and monitor
 norms to the end, so its currents are bitwise those of the step loop; its
 per-step codes are those the step loop returns.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -72,21 +74,29 @@ def test_march_reports_per_step_codes_like_the_step_loop():
     assert rcs[0 if first < (nt - 1) // 3 else 1] == tdbem.EUNSTABLE
 
 
-@pytest.mark.parametrize("mode,nr,limit", [(tdbem.MODE_IFMM, 1, 0.0), (tdbem.MODE_IFMM, 2, 1e6),
-                                           (tdbem.MODE_DIRECT, 1, 1e6)])
-def test_graph_march_equals_plain_march_bitwise(mode, nr, limit):
+@pytest.mark.parametrize("mode,nr,limit,form", [(tdbem.MODE_IFMM, 1, 0.0, "fp64"), (tdbem.MODE_IFMM, 2, 1e6, "fp64"),
+                                                (tdbem.MODE_DIRECT, 1, 1e6, "fp64"),
+                                                (tdbem.MODE_IFMM, 1, 1e6, "fp32+learned")])
+def test_graph_march_equals_plain_march_bitwise(mode, nr, limit, form):
     """graph = 1: each step's kernels before and after the device solve are
     replays of captured HIP graphs whose arguments are refreshed step by step
     (one executable before the solve, one per pattern of gated far-field
     levels after it).  Over 89 steps in two calls (a host wait between them)
     every step's currents are bitwise those of the plain march, and so are
     the per-step codes; the executables are built once per pattern and then
-    only refreshed."""
+    only refreshed.  The last case captures the FP32 form's kernels and the
+    learned initial guess (network and residual judge) as well."""
     torch = _torch()
     v, f = icosphere(2)
     cfg = dict(dt=0.078 / C0, mode=mode, leaf_max=6, gmres_rtol=1e-12, gmres_maxit=200, growth_limit=limit)
+    if form == "fp32+learned":
+        cfg.update(precision=tdbem.FP32, guess=tdbem.GUESS_LEARNED)
     A = tdbem.Solver(v, f, tdbem.Config(**cfg, n_rhs=nr))
     B = tdbem.Solver(v, f, tdbem.Config(**cfg, n_rhs=nr, graph=1))
+    if form == "fp32+learned":
+        w = np.load(os.path.join(os.path.dirname(tdbem.__file__), "weights", "guess_mlp_icosphere5120.npy"))
+        A.guess_weights(w)
+        B.guess_weights(w)
     nt = 90
     pulses = [gaussian_pulse(150e6 + 30e6 * r, 100e6) for r in range(nr)]
     V = torch.zeros((nt - 1, nr, A.ne), dtype=torch.float64, device="cuda")
@@ -104,7 +114,10 @@ def test_graph_march_equals_plain_march_bitwise(mode, nr, limit):
         codes.append(list(st1) + list(st2))
     builds, updates = B.query_array(tdbem.Q_GRAPHS, 2, np.int64).tolist()
     plain = A.query_array(tdbem.Q_GRAPHS, 2, np.int64).tolist()
-    print(f"graph march: {builds} executables built, {updates} refreshes over {nt - 1} steps")
+    used = (A.guess_used(), B.guess_used())
+    print(f"graph march: {builds} executables built, {updates} refreshes over {nt - 1} steps; "
+          f"learned guess taken {used[0]} / {used[1]} times")
+    assert used[0] == used[1]
     A.close()
     B.close()
     assert codes[0] == codes[1] and all(c == tdbem.OK for c in codes[0])
