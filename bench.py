@@ -106,7 +106,7 @@ def copy_probe(torch, mib=512):
 
 def physical_cores():
     """Physical cores from lscpu (unique core, socket pairs), capped by the
-    OpenMP thread count the host grants (the GPU machine's CPU share)."""
+    OpenMP thread count the host grants (its CPU share)."""
     n = 0
     try:
         out = subprocess.run(["lscpu", "-p=core,socket"], capture_output=True, text=True, timeout=10).stdout
