@@ -212,10 +212,12 @@ def test_all_pairs_count_and_config_in_effect():
                                          ("gmres_restart", 33), ("dt2", 3), ("solver", 2), ("growth_limit", -1.0),
                                          ("box_widen", 2), ("p_s", 5), ("p_s", 6), ("m2l", 7),
                                          ("m2l+fp32", tdbem.M2L_FFT), ("m2l+p6", tdbem.M2L_BF16),
-                                         ("near_kernel", 8), ("near_kernel", 9), ("autotune", 2)])
+                                         ("near_kernel", 8), ("near_kernel", 9), ("autotune", 2),
+                                         ("graph", 2), ("graph+host", 1), ("near_kernel+rhs", 3)])
 def test_invalid_configuration_fields(field, value):
     """(p_s = 6 with p_t = 4: the orders must agree; the Fourier-domain M2L with
-    FP32.)"""
+    FP32; the graph march needs the device solver; with several right-hand
+    sides only near_kernel 1 and 8 exist.)"""
     _torch()
     v, f = icosphere(1)
     cfg = tdbem.Config(dt=0.1 / C0, mode=tdbem.MODE_IFMM, leaf_max=6)
@@ -223,6 +225,10 @@ def test_invalid_configuration_fields(field, value):
         field, cfg.precision = "m2l", tdbem.FP32
     if field == "m2l+p6":                 # the bf16 M2L is built for p = 4
         field, cfg.p_s, cfg.p_t = "m2l", 6, 6
+    if field == "graph+host":             # graphs wrap the device solve's launches
+        field, cfg.solver = "graph", tdbem.SOLVER_HOST
+    if field == "near_kernel+rhs":        # a one-rhs form with two right-hand sides
+        field, cfg.n_rhs = "near_kernel", 2
     setattr(cfg, field, value)
     with pytest.raises(tdbem.TdbemError) as e:
         tdbem.Solver(v, f, cfg)
