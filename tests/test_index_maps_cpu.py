@@ -60,6 +60,137 @@ def test_near_jds_offsets_address_the_pair_and_lag():
     assert min(addr) == 0 and max(addr) == lens.sum() - 1
 
 
+def near_leaf_visits(lens, NU, NC):
+    """(pair, lag, coefficient address) visits of k_near_leaf for one row:
+    lanes 16 pairs x 4 lags with the pairs fastest (pg = lane & 15, sub =
+    lane >> 4), chunks of 64 NC pairs, rounds of NU steps of 4 lags."""
+    np_ = len(lens)
+    CH, NG = 64 * NC, 4 * NC
+    L = max(lens)
+    nl = [sum(1 for x in lens if x > l) for l in range(L)]
+    off = np.concatenate([[0], np.cumsum(nl)[:-1]]).astype(int)
+    seen, quarters = [], {}
+    for c0 in range(0, np_, CH):
+        cnt = min(CH, np_ - c0)
+        lmax = lens[c0]
+        for lane in range(64):
+            pg, sub = lane & 15, lane >> 4
+            for g in range(NG):
+                q = 16 * g + pg
+                ln = lens[c0 + q] if q < cnt else 0
+                for lb in range(0, lmax, 4 * NU):
+                    for t in range(NU):
+                        l = lb + 4 * t + sub
+                        if l < ln:
+                            a = off[l] + c0 + 16 * g + pg
+                            seen.append((c0 + q, l, a))
+                            quarters.setdefault((c0, g, lb, t, sub), []).append((pg, a))
+    return seen, quarters, off
+
+
+@pytest.mark.parametrize("NU,NC", [(2, 2), (1, 2)])
+@pytest.mark.parametrize("seed", range(4))
+def test_near_leaf_rounds_visit_each_coefficient_once_in_whole_lines(NU, NC, seed):
+    """Every (pair, lag) once, at its jagged-diagonal address; the lanes of one
+    quarter-wave read consecutive values (consecutive pairs at one lag)."""
+    rng = np.random.default_rng(100 + seed)
+    np_ = int(rng.integers(1, 400))
+    lens = sorted(rng.integers(1, 24, size=np_).tolist(), reverse=True)
+    seen, quarters, off = near_leaf_visits(lens, NU, NC)
+    want = [(p, l) for p in range(np_) for l in range(lens[p])]
+    assert sorted((p, l) for p, l, _ in seen) == sorted(want)
+    assert all(a == off[l] + p for p, l, a in seen)
+    for lanes in quarters.values():
+        lanes.sort()
+        pgs = [pg for pg, _ in lanes]
+        addr = [a for _, a in lanes]
+        assert pgs == list(range(pgs[0], pgs[0] + len(pgs)))        # the active lanes are a prefix run
+        assert addr == list(range(addr[0], addr[0] + len(addr)))    # consecutive values
+
+
+def leaf_window(pairs):
+    """The compressed window of a leaf as the set-up builds it: per source the
+    lags its strips reach, laid end to end; per pair its window word."""
+    srcs = sorted({j for j, _, _ in pairs})
+    lo = {j: min(g0 for jj, g0, n in pairs if jj == j) for j in srcs}
+    hi = {j: max(g0 + n - 1 for jj, g0, n in pairs if jj == j) for j in srcs}
+    woff, w = {}, 0
+    for j in srcs:
+        woff[j] = w
+        w += hi[j] - lo[j] + 1
+    words = [(woff[j] + g0 - lo[j]) | (n << 16) for j, g0, n in pairs]
+    recs = [(j, lo[j], woff[j], hi[j] - lo[j] + 1) for j in srcs]
+    return words, recs, w
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_near_leaf_window_words_address_the_staged_current(seed):
+    """W[o_s + w] holds J at lag a_s + w of source s (staging); the pair word
+    (offset | length << 16) plus lag l addresses source j's lag g0 + l, inside
+    j's part of the window; every window slot is staged once."""
+    rng = np.random.default_rng(200 + seed)
+    nsrc = int(rng.integers(1, 60))
+    pairs = []
+    for _ in range(int(rng.integers(1, 300))):
+        j = int(rng.integers(0, nsrc))
+        pairs.append((j, int(rng.integers(2, 40)), int(rng.integers(1, 12))))
+    words, recs, w = leaf_window(pairs)
+    staged = {}
+    for j, a, o, n in recs:
+        for k in range(n):
+            assert o + k not in staged
+            staged[o + k] = (j, a + k)
+    assert sorted(staged) == list(range(w))
+    for (j, g0, n), word in zip(pairs, words):
+        assert word >> 16 == n and (word & 0xFFFF) + n <= w < 65536
+        for l in range(n):
+            assert staged[(word & 0xFFFF) + l] == (j, g0 + l)
+
+
+@pytest.mark.parametrize("nrest,chunks,WPB", [(0, [(0, 0, 64), (1, 64, 100)], 16), (37, [(0, 0, 5)], 16),
+                                               (16, [], 16), (5, [(2, 7, 71), (0, 0, 7)], 8)])
+def test_near_leaf_blocks_cover_every_row_once(nrest, chunks, WPB):
+    """The first ceil(nrest / WPB) blocks take the listed rows, a wavefront
+    each; every other block one chunk, its wavefronts rows ra + wv, + WPB, ..."""
+    rest = list(range(1000, 1000 + nrest))
+    nrb = -(-nrest // WPB)
+    rows = []
+    for b in range(nrb + len(chunks)):
+        for wv in range(WPB):
+            if b < nrb:
+                idx = b * WPB + wv
+                if idx < nrest:
+                    rows.append(rest[idx])
+                continue
+            _, ra, rb = chunks[b - nrb]
+            rows.extend(range(ra + wv, rb, WPB))
+    want = rest + [r for _, ra, rb in chunks for r in range(ra, rb)]
+    assert sorted(rows) == sorted(want) and len(set(rows)) == len(rows)
+
+
+# ------------------------------------------------------------------ batched near field, matrix cores
+def test_leaf_mm_staging_covers_each_chunk_element_once():
+    """KC = 32 columns of A (64 rows) and 32 window rows (64 rhs) per chunk,
+    256 threads, 8 consecutive values each."""
+    a, b = [], []
+    for tid in range(256):
+        ar, ac = tid >> 2, 8 * (tid & 3)
+        bk, bc = tid >> 3, 8 * (tid & 7)
+        a += [(ar, ac + e) for e in range(8)]
+        b += [(bk, bc + e) for e in range(8)]
+    assert sorted(a) == [(r, c) for r in range(64) for c in range(32)]
+    assert sorted(b) == [(k, c) for k in range(32) for c in range(64)]
+
+
+@pytest.mark.parametrize("kpad", [4, 2048, 2052, 9000])
+def test_leaf_mm_segments_partition_the_columns(kpad):
+    """Column segments of at most 2048 per leaf: a partition of [0, kpad), and
+    the chunks of 32 inside a segment stop at its end."""
+    seg = [(k, min(kpad, k + 2048)) for k in range(0, kpad, 2048)]
+    cols = [c for kb, ke in seg for k0 in range(kb, ke, 32) for c in range(k0, min(k0 + 32, ke))]
+    assert cols == list(range(kpad))
+
+
 # ------------------------------------------------------------------ GMRES
 GM_THREADS, GM_RU, GM_RC = 1024, 12, 4
 
