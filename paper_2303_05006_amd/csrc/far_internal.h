@@ -11,12 +11,14 @@ static constexpr int NCH = 7;        // channels: 0-2 vector, 3 scalar, 4-6 magn
 static constexpr int M2L_NT = 64;    // columns per M2L tile
 static constexpr int NV_MAX = 4;     // moment variants per interval: full + up to 3 truncated (M_t >= 1)
 static constexpr int PMAX = 8;       // largest interpolation order
+static constexpr int M2L_SPLIT_BLOCKS = 2048;   // fewer offset-major M2L tiles than this: split the lags
 
 struct FarLevel {
     int n = 0, M = 0;
     int W = 0, WR = 0, NV = 0;   // window, ring slots (W + 1), moment variants per slot (full + truncated)
     double ds = 0, hs = 0, hn = 0, ht = 0;   // cell side, cell half-width, node half-width, time half-width
     int *il_off = nullptr, *il_src = nullptr, *il_code = nullptr;  // interaction lists
+    int64_t nil = 0;                                               // interaction-list entries
     int *ix = nullptr;                                             // [n][3] integer coords
     int *ebeg = nullptr, *eend = nullptr;
     int nleaf = 0, nparent = 0;
@@ -33,7 +35,9 @@ struct FarLevel {
     int ntile = 0;
     int *tile_code = nullptr, *tile_kind = nullptr, *tile_col0 = nullptr, *tile_ncol = nullptr;
     int *col_q = nullptr, *col_ch = nullptr;
-    double *YB = nullptr;     // [interaction-list entries][NCH][NN]
+    double *YB = nullptr;     // [lag groups][interaction-list entries][NCH][NN]
+    int yg_max = 1;           // lag groups YB holds (coarse levels split their window over blocks)
+    int yg = 1;               // lag groups of the last launch (summed by the reduce)
     // Fourier-domain M2L: transformed kernels, moments (ring) and local sums
     int *fft_code_slot = nullptr;   // [343]: offset code -> row of KH (-1: absent)
     double2 *KH = nullptr;          // [used offset][W][2][NF]

@@ -319,7 +319,13 @@ void ifmm_setup(tdbem_ctx *C) {
             FL.ntile = (int)tc.size();
             FL.tile_code = fup(C, tc); FL.tile_kind = fup(C, tk); FL.tile_col0 = fup(C, t0); FL.tile_ncol = fup(C, tn);
             FL.col_q = fup(C, cq); FL.col_ch = fup(C, cch);
-            FL.YB = falloc<double>(C, L.il_src.size() * NCH * NN);
+            // a level of few tiles splits its lag window over up to W blocks per
+            // tile (about 2048 blocks: eight per CU), each group writing its
+            // own copy of the per-entry sums
+            FL.nil = (int64_t)L.il_src.size();
+            FL.yg_max = FL.ntile > 0 && FL.ntile < M2L_SPLIT_BLOCKS
+                            ? std::min(FL.W, (M2L_SPLIT_BLOCKS + FL.ntile - 1) / FL.ntile) : 1;
+            FL.YB = falloc<double>(C, (size_t)FL.yg_max * L.il_src.size() * NCH * NN);
         }
     }
     // per-edge P2M / L2P weights at the interior 3-point rule of both triangles
@@ -587,15 +593,17 @@ __global__ void __launch_bounds__(256) k_m2m(const int *parent_cells, const int 
     }
 }
 
-// LC(O) = PEND(O, parity) + sum over O's interaction-list entries of YB (target-owned, fixed order)
+// LC(O) = PEND(O, parity) + sum over O's interaction-list entries of YB, and
+// over the lag groups of each entry (target-owned, fixed order)
 template <int P>
-__global__ void __launch_bounds__(256) k_m2l_reduce(int n, const int *il_off, const double *YB, const double *PEND,
-                                                    int parity, double *LC) {
+__global__ void __launch_bounds__(256) k_m2l_reduce(int n, const int *il_off, const double *YB, int ng,
+                                                    size_t gstride, const double *PEND, int parity, double *LC) {
     constexpr int NN = Dim<P>::NN;
     int O = blockIdx.x, c = blockIdx.y;
     for (int v = threadIdx.x; v < NN; v += 256) {
         double s = PEND[(((size_t)O * 2 + parity) * NCH + c) * NN + v];
-        for (int q = il_off[O]; q < il_off[O + 1]; ++q) s += YB[((size_t)q * NCH + c) * NN + v];
+        for (int q = il_off[O]; q < il_off[O + 1]; ++q)
+            for (int g = 0; g < ng; ++g) s += YB[g * gstride + ((size_t)q * NCH + c) * NN + v];
         LC[((size_t)O * NCH + c) * NN + v] = s;
     }
 }
@@ -846,6 +854,7 @@ static void m2l_level(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
         m2l_fft_level(C, FL, k, s);      // writes LC itself
         return;
     }
+    FL.yg = 1;                            // the tuned FP64 / FP32 kernel may split the lags
     if (P == 4 && !C->far->generic_m2l) {
         if (C->far->bf16_m2l) m2l_bf16_launch(C, FL, k, s);
         else if (f64) m2l_p4_launch<double>(C, FL, k, s);
@@ -855,8 +864,8 @@ static void m2l_level(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
     }
     if (C->nrhs == 1) {
         PhaseScope ps(C->prof, TDBEM_PH_M2L_SUM, s);
-        hipLaunchKernelGGL(k_m2l_reduce<P>, dim3(FL.n, NCH), dim3(256), 0, s, FL.n, FL.il_off, FL.YB, FL.PEND,
-                           (k + 1) & 1, FL.LC);
+        hipLaunchKernelGGL(k_m2l_reduce<P>, dim3(FL.n, NCH), dim3(256), 0, s, FL.n, FL.il_off, FL.YB, FL.yg,
+                           (size_t)FL.nil * NCH * Dim<P>::NN, FL.PEND, (k + 1) & 1, FL.LC);
         TD_HIP(hipGetLastError());
     }
 }

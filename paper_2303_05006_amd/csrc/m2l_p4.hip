@@ -4,6 +4,8 @@
 // channels sharing an offset), target-major for batched right-hand sides.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "far_internal.h"
 #include "mfma.h"
 
@@ -152,7 +154,10 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
                                                          const int *tile_col0, const int *tile_ncol, const int *col_q,
                                                          const int *col_ch, const int *il_src, const double *MM, int WR,
                                                          int NV, int k, int W, double hn, double ds, double ht, double cl,
-                                                         double *YB, const float *MMf, int kindA) {
+                                                         double *YB, const float *MMf, int kindA, int lag_per,
+                                                         size_t gstride) {
+    // blockIdx.y: the group of lags 1 + y lag_per .. (y + 1) lag_per of the
+    // window, written to its own copy of YB (coarse levels: more blocks)
     const int tile = blockIdx.x;
     const int code = tile_code[tile], kind = tile_kind[tile], col0 = tile_col0[tile], ncol = tile_ncol[tile];
     const int kfun = kind == 0 ? kindA : 1;     // vector-potential channels: the placement's kernel
@@ -176,7 +181,9 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
         cbase[tid] = b;
     }
     const int xr = tid & (NN / 2 - 1), xg = tid >> 7;   // row pair, first column
-    const int nlag = min(W, k + 1);               // lags whose source interval exists
+    const int lag0 = 1 + (int)blockIdx.y * lag_per;
+    const int nlag = min(min(W, k + 1), lag0 + lag_per - 1);   // lags whose source interval exists, in the group
+    YB += blockIdx.y * gstride;
     // source interval k + 1 - lag; the window's oldest intervals take the
     // variant truncated at the oldest interval's start
     auto var = [&](int lag) { return W - lag < NV - 1 ? W - lag + 1 : 0; };
@@ -201,8 +208,8 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
             }
         };
         __syncthreads();                          // cbase, rd and ird visible
-        fetch4(loff4(1));
-        for (int lag = 1; lag <= nlag; ++lag) {
+        fetch4(loff4(lag0));
+        for (int lag = lag0; lag <= nlag; ++lag) {
             __syncthreads();                      // the previous products are done with X and tab
 #pragma unroll
             for (int i = 0; i < M2L_NT / 8; ++i) *reinterpret_cast<float4 *>(&X[xh + 8 * i][4 * xq]) = p4[i];
@@ -214,8 +221,8 @@ __global__ void __launch_bounds__(M2L_THREADS, sizeof(T) == 4 ? 4 : 2) k_m2l_off
     } else {
         typename M2lPair<T>::type pre[M2L_PRE];
         __syncthreads();                          // cbase, rd and ird visible
-        m2l_fetch<T>(pre, cbase, MM, loff(1), xg);
-        for (int lag = 1; lag <= nlag; ++lag) {
+        m2l_fetch<T>(pre, cbase, MM, loff(lag0), xg);
+        for (int lag = lag0; lag <= nlag; ++lag) {
             __syncthreads();                      // the previous products are done with X and tab
             m2l_store<T>(X, pre, xr, xg);
             m2l_table<T>(tab, rd, ird, lag, kfun, cgt, 2.0 * cl);
@@ -382,10 +389,15 @@ void m2l_p4_launch(tdbem_ctx *C, FarLevel &FL, int k, hipStream_t s) {
     const int kindA = m2l_kind_a(C->cfg);
     if (nr == 1) {
         if (FL.ntile > 0) {
+            // lag groups: as many as YB holds and the window's lags allow, none empty
+            const int nlag = std::min(FL.W, k + 1);
+            const int per = (nlag + std::min(FL.yg_max, nlag) - 1) / std::min(FL.yg_max, nlag);
+            FL.yg = (nlag + per - 1) / per;
             PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
-            hipLaunchKernelGGL(k_m2l_off<T>, dim3(FL.ntile), dim3(M2L_THREADS), 0, s, FL.tile_code, FL.tile_kind,
-                               FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, FL.WR, FL.NV, k, FL.W,
-                               FL.hn, FL.ds, FL.ht, C->c, FL.YB, (const float *)FL.MM32, kindA);
+            hipLaunchKernelGGL(k_m2l_off<T>, dim3(FL.ntile, FL.yg), dim3(M2L_THREADS), 0, s, FL.tile_code,
+                               FL.tile_kind, FL.tile_col0, FL.tile_ncol, FL.col_q, FL.col_ch, FL.il_src, FL.MM, FL.WR,
+                               FL.NV, k, FL.W, FL.hn, FL.ds, FL.ht, C->c, FL.YB, (const float *)FL.MM32, kindA, per,
+                               (size_t)FL.nil * NCH * NN);
         }
     } else {
         PhaseScope ps(C->prof, TDBEM_PH_M2L, s);
