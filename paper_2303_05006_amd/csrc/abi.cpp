@@ -62,6 +62,8 @@ void launch_scatter_out(const tdbem_ctx *C, const double *src, double *dst, hipS
 void launch_axpby(int64_t n, double a, const double *x, double b, double *y, hipStream_t s);
 void launch_ring_put(const tdbem_ctx *C, int slot, const double *x, hipStream_t s);
 void launch_extrap(const tdbem_ctx *C, int alpha, double *x, hipStream_t s);
+void launch_rhs_finish(const tdbem_ctx *C, int alpha, const double *far, hipStream_t s);
+void launch_ring_out(const tdbem_ctx *C, int slot, double *Jout, hipStream_t s);
 void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 void launch_near_to_jds(const tdbem_ctx *C, const int64_t *src_off, const double *src, hipStream_t s);
 void launch_gather_vals(const double *val, const int64_t *idx, int64_t n, double *out, hipStream_t s);
@@ -680,7 +682,6 @@ struct MarchRec {
 // the kernels of a step before the solve: tested field in, monitor norm,
 // near-field history sum, right-hand side, far field, initial guess
 static void step_pre(tdbem_ctx *C, const double *V, int a, bool monitor, hipStream_t s) {
-    const int64_t nv = (int64_t)C->ne * C->nrhs;
     {
         PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
         launch_gather_in(C, V, C->d_rhs, s);
@@ -689,9 +690,7 @@ static void step_pre(tdbem_ctx *C, const double *V, int a, bool monitor, hipStre
     { PhaseScope ps(C->prof, TDBEM_PH_NEAR, s); launch_near(C, a, C->d_tmp, 1.0, s); }
     {
         PhaseScope ps(C->prof, TDBEM_PH_OTHER, s);
-        launch_axpby(nv, -1.0, C->d_tmp, 1.0, C->d_rhs, s);
-        if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_subtract_far(C, a, C->d_rhs, s);
-        launch_extrap(C, a, C->d_x, s);
+        launch_rhs_finish(C, a, C->cfg.mode == TDBEM_MODE_IFMM ? ifmm_far_slot(C, a) : nullptr, s);
         if (guess_active(C)) launch_guess(C, a, s);
     }
 }
@@ -708,9 +707,8 @@ static void step_rec(tdbem_ctx *C, const int *dflag, MarchRec *rec, bool monitor
 
 // the kernels of a step after the solve: ring, far field, current out
 static void step_post(tdbem_ctx *C, double *Jout, int a, hipStream_t s) {
-    { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_ring_put(C, (a - 1) & (C->ring - 1), C->d_x, s); }
+    { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_ring_out(C, (a - 1) & (C->ring - 1), Jout, s); }
     if (C->cfg.mode == TDBEM_MODE_IFMM) ifmm_after_solve(C, a, s);
-    if (Jout) { PhaseScope ps(C->prof, TDBEM_PH_OTHER, s); launch_scatter_out(C, C->d_x, Jout, s); }
 }
 
 static int step_impl(tdbem_ctx *C, const double *V, double *Jout, bool solve, const double *Jgiven,

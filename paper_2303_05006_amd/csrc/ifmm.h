@@ -8,6 +8,7 @@ void ifmm_reset(tdbem_ctx *C);                                   // zero all far
 void ifmm_destroy(tdbem_ctx *C);
 // rhs[e][r] -= far-field potential deposited for step alpha (target slot alpha-1)
 void ifmm_subtract_far(tdbem_ctx *C, int alpha, double *rhs, hipStream_t s);
+const double *ifmm_far_slot(const tdbem_ctx *C, int alpha);
 // out[e][r] += far-field potential deposited for step alpha
 void ifmm_add_far(tdbem_ctx *C, int alpha, double *out, hipStream_t s);
 // after J^{alpha-1} is in the history ring: upward/downward passes at time gates

@@ -950,6 +950,12 @@ __global__ void k_far_apply(int64_t n, double sign, const double *FAR, double *y
 }
 
 // ------------------------------------------------------------------ driver
+// this step's far-field potential (the slot L2P wrote for step alpha)
+const double *ifmm_far_slot(const tdbem_ctx *C, int alpha) {
+    const FarState *F = C->far;
+    return F->FAR + (size_t)((alpha - 1) & (F->FR - 1)) * C->ne * C->nrhs;
+}
+
 void ifmm_subtract_far(tdbem_ctx *C, int alpha, double *rhs, hipStream_t s) {
     FarState *F = C->far;
     int64_t n = (int64_t)C->ne * C->nrhs;

@@ -655,7 +655,6 @@ __global__ void k_scatter_out(int ne, int nrhs, const int *perm, const double *s
     int e = perm[p];
     for (int r = 0; r < nrhs; ++r) dst[(size_t)r * ne + e] = src[(size_t)p * nrhs + r];
 }
-// y = a*x + b*y over n values
 // word copy (a kernel rather than a copy command, so that it can sit in a
 // captured graph like the step's other work)
 __global__ void k_copy_words(size_t n, const uint32_t *__restrict__ src, uint32_t *__restrict__ dst) {
@@ -675,6 +674,7 @@ __global__ void k_fill(int64_t n, double v, double *p) {
     if (i < n) p[i] = v;
 }
 
+// y = a*x + b*y over n values
 __global__ void k_axpby(int64_t n, double a, const double *x, double b, double *y) {
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) y[k] = a * x[k] + b * y[k];
@@ -696,6 +696,51 @@ __global__ void k_extrap(int ne, int nrhs, int R, int alpha, const double *ring,
     const double *J = ring + (size_t)e * R * nrhs + r;
     auto at = [&](int b) { return b < 0 ? 0.0 : J[(size_t)(b & (R - 1)) * nrhs]; };
     x[k] = 3.0 * at(alpha - 2) - 3.0 * at(alpha - 3) + at(alpha - 4);
+}
+
+// The step's right-hand side once the near-field sum is in: rhs -= near,
+// rhs -= far (this step's far-field potential, IFMM), and the extrapolated
+// initial guess x (as k_extrap); one pass for the three
+__global__ void k_rhs_finish(int ne, int nrhs, int R, int alpha, const double *__restrict__ near,
+                             const double *__restrict__ far, double *__restrict__ rhs, const double *__restrict__ ring,
+                             double *__restrict__ x) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    double v = rhs[k] - near[k];
+    if (far) v -= far[k];
+    rhs[k] = v;
+    int e = (int)(k / nrhs), r = (int)(k % nrhs);
+    const double *J = ring + (size_t)e * R * nrhs + r;
+    auto at = [&](int b) { return b < 0 ? 0.0 : J[(size_t)(b & (R - 1)) * nrhs]; };
+    x[k] = 3.0 * at(alpha - 2) - 3.0 * at(alpha - 3) + at(alpha - 4);
+}
+
+// After the solve: the ring slot (and its FP32 copy) and, if asked, the
+// current in the caller's order (as k_ring_put and k_scatter_out)
+__global__ void k_ring_out(int ne, int nrhs, int R, int slot, const double *__restrict__ x, double *__restrict__ ring,
+                           float *__restrict__ ring32, const int *__restrict__ perm, double *__restrict__ Jout) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= (int64_t)ne * nrhs) return;
+    int e = (int)(k / nrhs), r = (int)(k % nrhs);
+    const size_t q = ((size_t)e * R + slot) * nrhs + r;
+    const double v = x[k];
+    ring[q] = v;
+    if (ring32) ring32[q] = (float)v;
+    if (Jout) Jout[(size_t)r * ne + perm[e]] = v;
+}
+
+void launch_rhs_finish(const tdbem_ctx *C, int alpha, const double *far, hipStream_t s) {
+    const int64_t n = (int64_t)C->ne * C->nrhs;
+    hipLaunchKernelGGL(k_rhs_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, alpha, C->d_tmp,
+                       far, C->d_rhs, C->d_Jring, C->d_x);
+    TD_HIP(hipGetLastError());
+}
+
+void launch_ring_out(const tdbem_ctx *C, int slot, double *Jout, hipStream_t s) {
+    const int64_t n = (int64_t)C->ne * C->nrhs;
+    hipLaunchKernelGGL(k_ring_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, C->ne, C->nrhs, C->ring, slot, C->d_x,
+                       C->d_Jring, C->d_Jring32, C->d_perm, Jout);
+    TD_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ GMRES
