@@ -98,6 +98,9 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
     const size_t budget = std::min<size_t>(near_leaf_lds_budget(C->near_L) / jt, 65535);
     const int crow = near_leaf_rows();
     std::vector<int> r0, r1, soff(1, 0), src, g, loc(nj.size(), 0), pwl(nj.size(), 0), ws, chunk, rest;
+    C->h_leaf_w.clear();
+    C->h_colmap.clear();
+    C->h_pcol.assign(C->nrhs > 1 ? nj.size() : 0, 0);
     size_t maxw = 0;
     for (int l = 0; l <= T.lmax; ++l) {
         const Level &Lv = T.lev[l];
@@ -131,6 +134,7 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
             }
             std::vector<int> woff(list.size());
             size_t w = 0;
+            const bool mm = C->nrhs > 1;       // the batched matrix-core form's column map
             for (size_t k = 0; k < list.size(); ++k) {
                 woff[k] = (int)std::min<size_t>(w, 1 << 30);
                 const int n = hi[k] >= lo[k] ? hi[k] - lo[k] + 1 : 0;
@@ -138,8 +142,18 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
                 ws.push_back(n > 0 ? lo[k] : 0);
                 ws.push_back(woff[k]);
                 ws.push_back(n);
+                if (mm)
+                    for (int t = 0; t < n; ++t) {
+                        C->h_colmap.push_back(list[k]);
+                        C->h_colmap.push_back(lo[k] + t);
+                    }
                 w += (size_t)n;
             }
+            TD_REQUIRE(w < (size_t)1 << 31, TDBEM_EINVAL, "a leaf's near-field window exceeds 2^31 columns");
+            C->h_leaf_w.push_back((int)w);
+            if (mm)
+                for (int q = nrow[a]; q < nrow[b]; ++q)
+                    C->h_pcol[q] = woff[loc[q]] + ((ngl[q] & 0xffff) - lo[loc[q]]);
             src.insert(src.end(), list.begin(), list.end());
             soff.push_back((int)src.size());
             if (w <= budget) {
@@ -170,12 +184,6 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
     NL.nleaves = (int)r0.size();
     C->h_leaf_r0 = r0;
     C->h_leaf_r1 = r1;
-    C->h_leaf_ns.resize(r0.size());
-    C->h_leaf_gw.resize(r0.size());
-    for (size_t i = 0; i < r0.size(); ++i) {
-        C->h_leaf_ns[i] = soff[i + 1] - soff[i];
-        C->h_leaf_gw[i] = g[2 * i + 1];
-    }
     C->leaf_cover = covered == (size_t)C->ne;
     if (near_leaf_sorted()) {
         // largest chunks (stored coefficients) first: the last blocks to start
@@ -210,28 +218,38 @@ static void build_near_leaves(tdbem_ctx *C, const std::vector<int> &nrow, const 
     NL.d_rest = dupload(C, rest);
 }
 
-void launch_leaf_mm_fill(const tdbem_ctx *C, int64_t np, const int *prow, const int64_t *psrc, const int *row_leaf,
-                         const int64_t *aoff, const int *kpad, const double *val, hipStream_t s);
+void launch_leaf_mm_fill(const tdbem_ctx *C, int64_t np, const int *prow, const int *pcol, const int64_t *psrc,
+                         const int *row_leaf, const int64_t *aoff, const int *kpad, const double *val, hipStream_t s);
 
 // Batched right-hand sides: the dense per-leaf coefficient blocks of the
-// matrix-core near field (rows x (sources x window), padded to 4 columns),
+// matrix-core near field (rows x the leaf's compressed window, padded to 4 columns),
 // filled from the pair-major set-up coefficients.  Skipped when the leaves do
 // not partition the rows or the blocks would exceed 32 GB.
 static void build_leaf_mm(tdbem_ctx *C, const std::vector<int> &nrow, const int64_t *d_psrc, const double *d_val) {
     if (!C->leaf_cover) return;
     const size_t nl = C->h_leaf_r0.size();
-    std::vector<int64_t> aoff(nl);
-    std::vector<int> kpad(nl), row_leaf(C->ne, 0);
-    int64_t tot = 0;
+    std::vector<int64_t> aoff(nl), coff(nl);
+    std::vector<int> kpad(nl), row_leaf(C->ne, 0), colmap;
+    int64_t tot = 0, ctot = 0, csrc = 0;
+    // a leaf's columns are its compressed window (per source the lags its
+    // strips reach), padded to a multiple of 4 with (edge 0, lag 0) columns
+    // whose coefficients stay zero
+    colmap.reserve(C->h_colmap.size() + 8 * nl);
     for (size_t i = 0; i < nl; ++i) {
-        const int K = C->h_leaf_ns[i] * C->h_leaf_gw[i];
+        const int K = C->h_leaf_w[i];
         kpad[i] = std::max(4, (K + 3) / 4 * 4);
         aoff[i] = tot;
+        coff[i] = ctot;
         tot += (int64_t)(C->h_leaf_r1[i] - C->h_leaf_r0[i]) * kpad[i];
+        colmap.insert(colmap.end(), C->h_colmap.begin() + 2 * csrc, C->h_colmap.begin() + 2 * (csrc + K));
+        colmap.resize(colmap.size() + 2 * (size_t)(kpad[i] - K), 0);
+        csrc += K;
+        ctot += kpad[i];
         for (int r = C->h_leaf_r0[i]; r < C->h_leaf_r1[i]; ++r) row_leaf[r] = (int)i;
     }
+    std::vector<int>().swap(C->h_colmap);
     const size_t vb = C->cfg.precision == TDBEM_FP64 ? sizeof(double) : sizeof(float);
-    if ((double)tot * vb > 32e9) return;
+    if ((double)tot * vb > 32e9) { std::vector<int>().swap(C->h_pcol); return; }
     std::vector<int> prow(nrow.back());
     for (int i = 0; i < C->ne; ++i)
         for (int q = nrow[i]; q < nrow[i + 1]; ++q) prow[q] = i;
@@ -246,12 +264,17 @@ static void build_leaf_mm(tdbem_ctx *C, const std::vector<int> &nrow, const int6
     }
     C->d_leaf_aoff = dupload(C, aoff);
     C->d_leaf_kpad = dupload(C, kpad);
+    C->d_leaf_coff = dupload(C, coff);
+    C->d_leaf_colmap = dupload(C, colmap);
     int *d_prow = dupload(C, prow);
+    int *d_pcol = dupload(C, C->h_pcol);
     C->d_row_leaf = dupload(C, row_leaf);
-    launch_leaf_mm_fill(C, (int64_t)prow.size(), d_prow, d_psrc, C->d_row_leaf, C->d_leaf_aoff, C->d_leaf_kpad, d_val,
-                        s);
+    launch_leaf_mm_fill(C, (int64_t)prow.size(), d_prow, d_pcol, d_psrc, C->d_row_leaf, C->d_leaf_aoff,
+                        C->d_leaf_kpad, d_val, s);
     TD_HIP(hipStreamSynchronize(s));
     dfree(C, d_prow, prow.size());
+    dfree(C, d_pcol, C->h_pcol.size());
+    std::vector<int>().swap(C->h_pcol);
     // column segments of at most LEAF_KSEG columns, one block each, so that
     // large leaves do not leave the other CUs idle; partial sums per segment
     constexpr int LEAF_KSEG = 2048;
@@ -270,6 +293,14 @@ static void build_leaf_mm(tdbem_ctx *C, const std::vector<int> &nrow, const int6
         leaf_seg.push_back((int)seg_leaf.size());
     }
     C->leaf_nseg = (int)seg_leaf.size();
+    std::vector<int> order(seg_leaf.size());
+    std::iota(order.begin(), order.end(), 0);
+    auto seg_work = [&](int g) {
+        const int lf = seg_leaf[g];
+        return (int64_t)(C->h_leaf_r1[lf] - C->h_leaf_r0[lf]) * (seg_k[2 * g + 1] - seg_k[2 * g]);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return seg_work(x) > seg_work(y); });
+    C->d_seg_order = dupload(C, order);
     C->d_seg_leaf = dupload(C, seg_leaf);
     C->d_seg_k = dupload(C, seg_k);
     C->d_seg_poff = dupload(C, seg_poff);
@@ -573,6 +604,8 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
         int64_t *d_src = dupload(C, nsrc);
         launch_near_to_jds(C, d_src, d_val, s);
         if (C->nrhs > 1 && cfg->precision != TDBEM_BF16) build_leaf_mm(C, nrow, d_src, d_val);
+        std::vector<int>().swap(C->h_colmap);     // set-up only
+        std::vector<int>().swap(C->h_pcol);
         TD_HIP(hipStreamSynchronize(s));
         dfree(C, d_src, nsrc.size());
     }

@@ -346,11 +346,12 @@ __global__ void __launch_bounds__(NEAR_LEAF_THREADS) __attribute__((amdgpu_waves
 // One block of 4 wavefronts per (leaf, 64 rhs); wavefront w owns rhs
 // 16 w .. 16 w + 15 and the rows in groups of 64 (4 row blocks of 16).
 template <typename T>
-__global__ void __launch_bounds__(256) k_near_leaf_mm(const int *__restrict__ seg_leaf, const int *__restrict__ seg_k,
+__global__ void __launch_bounds__(256) k_near_leaf_mm(const int *__restrict__ seg_order,
+                                                      const int *__restrict__ seg_leaf, const int *__restrict__ seg_k,
                                                       const int64_t *__restrict__ seg_poff,
                                                       const int *__restrict__ leaf_r0, const int *__restrict__ leaf_r1,
-                                                      const int *__restrict__ leaf_soff, const int *__restrict__ leaf_src,
-                                                      const int *__restrict__ leaf_g, const int64_t *__restrict__ aoff,
+                                                      const int64_t *__restrict__ coff, const int2 *__restrict__ colmap,
+                                                      const int64_t *__restrict__ aoff,
                                                       const int *__restrict__ kpad, const T *__restrict__ A,
                                                       const T *__restrict__ ring, int ring_mask, int nrhs, int alpha,
                                                       double *__restrict__ part) {
@@ -358,16 +359,17 @@ __global__ void __launch_bounds__(256) k_near_leaf_mm(const int *__restrict__ se
     // columns of A (64 rows) and KC rows of J (64 rhs) staged in LDS with
     // coalesced loads, the next chunk's loads in flight during this chunk's
     // products; the segment's partial sums go to part (summed per leaf in a
-    // fixed order by k_near_leaf_sum)
+    // fixed order by k_near_leaf_sum).  Blocks take the segments largest
+    // first (seg_order), and skip the products of 16-row blocks past the
+    // leaf's rows.
     constexpr int KC = 32, AS = KC + (sizeof(T) == 8 ? 1 : 2), BS = 64 + (sizeof(T) == 8 ? 1 : 2);
     __shared__ T As[64][AS];
     __shared__ T Bs[KC][BS];
-    const int sg = blockIdx.x, lf = seg_leaf[sg];
+    const int sg = seg_order[blockIdx.x], lf = seg_leaf[sg];
     const int kb = seg_k[2 * sg], ke = seg_k[2 * sg + 1];
     const int nr = leaf_r1[lf] - leaf_r0[lf];
-    const int s0 = leaf_soff[lf];
-    const int gmin = leaf_g[2 * lf], gw = leaf_g[2 * lf + 1];
-    const int K = (leaf_soff[lf + 1] - s0) * gw, KP = kpad[lf];
+    const int KP = kpad[lf];
+    const int2 *cm = colmap + coff[lf];    // column k: (source edge, lag) of the leaf's window
     const T *Al = A + aoff[lf];
     double *P = part + seg_poff[sg];
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
@@ -391,9 +393,9 @@ __global__ void __launch_bounds__(256) k_near_leaf_mm(const int *__restrict__ se
             }
             const int k = k0 + bk;
             const T *jr = nullptr;
-            if (k < ke && k < K) {
-                const int sl = k / gw, w = k % gw;
-                jr = ring + ((size_t)leaf_src[s0 + sl] * R + ((alpha - gmin - w) & ring_mask)) * nrhs;
+            if (k < ke) {
+                const int2 c = cm[k];
+                jr = ring + ((size_t)c.x * R + ((alpha - c.y) & ring_mask)) * nrhs;
             }
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
@@ -416,7 +418,9 @@ __global__ void __launch_bounds__(256) k_near_leaf_mm(const int *__restrict__ se
                 const int kk = 4 * ks + (lane >> 4);
                 const T bv = Bs[kk][16 * wv + (lane & 15)];
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb) acc[rb] = Mma<T>::op(As[16 * rb + (lane & 15)][kk], bv, acc[rb]);
+                for (int rb = 0; rb < 4; ++rb)
+                    if (rg + 16 * rb < nr)       // uniform: row blocks past the leaf's rows add nothing
+                        acc[rb] = Mma<T>::op(As[16 * rb + (lane & 15)][kk], bv, acc[rb]);
             }
         }
         const int col = c0 + 16 * wv + (lane & 15);
@@ -448,30 +452,30 @@ __global__ void k_near_leaf_sum(int ne, int nrhs, const int *__restrict__ row_le
 // the dense leaf blocks from the pair-major coefficients: one thread per
 // pair, its strip written at (row, source index gw + lag - gmin)
 template <typename T>
-__global__ void k_leaf_mm_fill(int64_t np, const int *__restrict__ prow, const int *__restrict__ ploc,
+__global__ void k_leaf_mm_fill(int64_t np, const int *__restrict__ prow, const int *__restrict__ pcol,
                                const int *__restrict__ pgl, const int64_t *__restrict__ psrc,
                                const int *__restrict__ row_leaf, const int *__restrict__ leaf_r0,
-                               const int *__restrict__ leaf_g, const int64_t *__restrict__ aoff,
-                               const int *__restrict__ kpad, const double *__restrict__ val, T *__restrict__ A) {
+                               const int64_t *__restrict__ aoff, const int *__restrict__ kpad,
+                               const double *__restrict__ val, T *__restrict__ A) {
+    // pair q's strip: columns pcol[q] .. + len - 1 of its row in the leaf's block
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= np) return;
     const int row = prow[q], lf = row_leaf[row];
-    const int g0 = pgl[q] & 0xffff, len = pgl[q] >> 16;
-    const int gmin = leaf_g[2 * lf], gw = leaf_g[2 * lf + 1];
-    T *a = A + aoff[lf] + (size_t)(row - leaf_r0[lf]) * kpad[lf] + (size_t)ploc[q] * gw + (g0 - gmin);
+    const int len = pgl[q] >> 16;
+    T *a = A + aoff[lf] + (size_t)(row - leaf_r0[lf]) * kpad[lf] + pcol[q];
     for (int l = 0; l < len; ++l) a[l] = (T)val[psrc[q] + l];
 }
 
-void launch_leaf_mm_fill(const tdbem_ctx *C, int64_t np, const int *prow, const int64_t *psrc, const int *row_leaf,
-                         const int64_t *aoff, const int *kpad, const double *val, hipStream_t s) {
+void launch_leaf_mm_fill(const tdbem_ctx *C, int64_t np, const int *prow, const int *pcol, const int64_t *psrc,
+                         const int *row_leaf, const int64_t *aoff, const int *kpad, const double *val, hipStream_t s) {
     const NearLeaves &NL = C->nleaf;
     const unsigned nb = (unsigned)((np + 255) / 256);
     if (C->d_leafA64)
-        hipLaunchKernelGGL(k_leaf_mm_fill<double>, dim3(nb), dim3(256), 0, s, np, prow, NL.d_loc, C->d_npair_gl, psrc,
-                           row_leaf, NL.d_r0, NL.d_g, aoff, kpad, val, C->d_leafA64);
+        hipLaunchKernelGGL(k_leaf_mm_fill<double>, dim3(nb), dim3(256), 0, s, np, prow, pcol, C->d_npair_gl, psrc,
+                           row_leaf, NL.d_r0, aoff, kpad, val, C->d_leafA64);
     if (C->d_leafA32)
-        hipLaunchKernelGGL(k_leaf_mm_fill<float>, dim3(nb), dim3(256), 0, s, np, prow, NL.d_loc, C->d_npair_gl, psrc,
-                           row_leaf, NL.d_r0, NL.d_g, aoff, kpad, val, C->d_leafA32);
+        hipLaunchKernelGGL(k_leaf_mm_fill<float>, dim3(nb), dim3(256), 0, s, np, prow, pcol, C->d_npair_gl, psrc,
+                           row_leaf, NL.d_r0, aoff, kpad, val, C->d_leafA32);
     TD_HIP(hipGetLastError());
 }
 
@@ -607,13 +611,13 @@ static void launch_near_t(const tdbem_ctx *C, const VT *val, const JT *ring, int
         const NearLeaves &NL = C->nleaf;
         const dim3 grid((unsigned)C->leaf_nseg, (unsigned)((C->nrhs + 63) / 64));
         if constexpr (sizeof(JT) == 8)
-            hipLaunchKernelGGL(k_near_leaf_mm<double>, grid, dim3(256), 0, s, C->d_seg_leaf, C->d_seg_k,
-                               C->d_seg_poff, NL.d_r0, NL.d_r1, NL.d_soff, NL.d_src, NL.d_g, C->d_leaf_aoff,
+            hipLaunchKernelGGL(k_near_leaf_mm<double>, grid, dim3(256), 0, s, C->d_seg_order, C->d_seg_leaf, C->d_seg_k,
+                               C->d_seg_poff, NL.d_r0, NL.d_r1, C->d_leaf_coff, (const int2 *)C->d_leaf_colmap, C->d_leaf_aoff,
                                C->d_leaf_kpad, C->d_leafA64, (const double *)ring, C->ring - 1, C->nrhs, alpha,
                                C->d_leaf_part);
         else
-            hipLaunchKernelGGL(k_near_leaf_mm<float>, grid, dim3(256), 0, s, C->d_seg_leaf, C->d_seg_k,
-                               C->d_seg_poff, NL.d_r0, NL.d_r1, NL.d_soff, NL.d_src, NL.d_g, C->d_leaf_aoff,
+            hipLaunchKernelGGL(k_near_leaf_mm<float>, grid, dim3(256), 0, s, C->d_seg_order, C->d_seg_leaf, C->d_seg_k,
+                               C->d_seg_poff, NL.d_r0, NL.d_r1, C->d_leaf_coff, (const int2 *)C->d_leaf_colmap, C->d_leaf_aoff,
                                C->d_leaf_kpad, C->d_leafA32, (const float *)ring, C->ring - 1, C->nrhs, alpha,
                                C->d_leaf_part);
         const int64_t n = (int64_t)C->ne * C->nrhs;

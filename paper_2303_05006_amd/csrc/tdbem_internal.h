@@ -196,13 +196,18 @@ struct tdbem_ctx {
     // batched rhs: dense per-leaf coefficient blocks for the matrix cores
     bool leaf_mm_ready = false;
     bool leaf_cover = false;        // the leaves' row ranges partition the rows
-    std::vector<int> h_leaf_r0, h_leaf_r1, h_leaf_ns, h_leaf_gw;   // per leaf: rows, sources, window
+    std::vector<int> h_leaf_r0, h_leaf_r1, h_leaf_w;   // per leaf: rows, compressed window (columns)
+    std::vector<int> h_pcol;        // set-up only: per pair the window column of its strip's first lag
+    std::vector<int> h_colmap;      // set-up only: per leaf window column (source edge, lag), leaves in turn
     int64_t *d_leaf_aoff = nullptr; // [leaves] first value of each leaf's block
     int *d_leaf_kpad = nullptr;     // [leaves] block row length (sources x window, padded to 4)
     double *d_leafA64 = nullptr;    // FP64 blocks (FP64 form)
     float *d_leafA32 = nullptr;     // FP32 blocks (FP32 form)
     int64_t leaf_mm_bytes = 0;      // bytes of the dense leaf blocks
     int leaf_nseg = 0;              // column segments (a block each) over all leaves
+    int *d_seg_order = nullptr;     // [segments] launch order: largest (rows x columns) first
+    int64_t *d_leaf_coff = nullptr; // [leaves] offset of the leaf's columns in the column map
+    int *d_leaf_colmap = nullptr;   // [columns][2] source edge and lag of every padded leaf column
     int *d_seg_leaf = nullptr;      // [segments] leaf
     int *d_seg_k = nullptr;         // [segments][2] column range
     int64_t *d_seg_poff = nullptr;  // [segments] offset of the segment's partial sums [rows][n_rhs]
