@@ -167,8 +167,9 @@ typedef struct {
                                  pair blocks per round, the default (form 5) when any leaf's window fits.
                                  Several rhs: 0 the row kernel (lanes are right-hand sides); 7 the
                                  per-leaf matrix-core form (each leaf's coefficients as a dense block over
-                                 its sources and lag window, multiplied by the sources' current window on
-                                 the matrix cores; FP64 and FP32 forms), the default when it is built */
+                                 its window: per source the lags its strips reach; multiplied by the
+                                 sources' currents at those lags on the matrix cores; FP64 and FP32 forms),
+                                 the default when it is built */
     int32_t graph;            /* 1: tdbem_march issues each step's kernels before and after the device solve
                                  as launches of HIP graphs captured from them (one graph for the kernels
                                  before the solve, one per pattern of far-field levels passing their time

@@ -302,8 +302,9 @@ def test_near_field_forms_agree_bitwise(mode, prec, level, cdt):
                                                     (tdbem.MODE_IFMM, tdbem.FP64, 5, 3, 0.01)])
 def test_batched_near_field_on_the_matrix_cores(mode, prec, nr, level, cdt):
     """Batched right-hand sides: the per-leaf matrix-core near field
-    (near_kernel 8: each leaf's coefficients as a dense block over its sources
-    and lag window, times the sources' current window) against the row kernel
+    (near_kernel 8: each leaf's coefficients as a dense block over its window,
+    per source the lags its strips reach, times the sources' currents at those
+    lags) against the row kernel (near_kernel 1)
     on the same history; 70 rhs spans two groups of 64 with a ragged second.
     FP64 to rounding of the sums; the FP32 form accumulates in FP32 on the
     matrix cores (the row kernel in FP64).  The last case (1280 triangles,
