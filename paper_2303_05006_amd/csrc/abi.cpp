@@ -53,7 +53,7 @@ Profiler::~Profiler() {
 }
 
 void launch_lag_range(const GeoDev &G, int64_t npairs, const int *pi, const int *pj, int *lo, int *hi, hipStream_t s);
-void launch_zfill(const GeoDev &G, int64_t nnz, int64_t npairs, const int *pi, const int *pj, const int *g0,
+void launch_zfill(const GeoDev &G, int64_t n, int64_t k0, int64_t npairs, const int *pi, const int *pj, const int *g0,
                   const int64_t *off, double *val, hipStream_t s);
 void launch_vinc(const GeoDev &G, int ne, int nrhs, const double *pulses, const int *perm, double t, double *V, hipStream_t s);
 void launch_near(const tdbem_ctx *C, int alpha, double *out, double scale, hipStream_t s);
@@ -505,6 +505,7 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     std::vector<int> pi, pj;
     build_near_pairs(C, pi, pj);
     int64_t np = (int64_t)pi.size();
+    if (C->trace) std::fprintf(stderr, "[tdbem] near pairs listed: %lld\n", (long long)np);
     int *d_pi = dalloc<int>(C, np), *d_pj = dalloc<int>(C, np);
     TD_HIP(hipMemcpy(d_pi, pi.data(), np * sizeof(int), hipMemcpyHostToDevice));
     TD_HIP(hipMemcpy(d_pj, pj.data(), np * sizeof(int), hipMemcpyHostToDevice));
@@ -524,7 +525,19 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
     }
     int64_t *d_off = dupload(C, off);
     double *d_val = dalloc<double>(C, nnz);
-    launch_zfill(G, nnz, np, d_pi, d_pj, d_lo, d_off, d_val, s);
+    if (C->trace) std::fprintf(stderr, "[tdbem] %lld pairs, %lld coefficients\n", (long long)np, (long long)nnz);
+    {
+        // in chunks, so that a trace shows progress on large problems
+        constexpr int64_t ZCHUNK = (int64_t)1 << 28;
+        for (int64_t c0 = 0; c0 < nnz; c0 += ZCHUNK) {
+            launch_zfill(G, std::min(ZCHUNK, nnz - c0), c0, np, d_pi, d_pj, d_lo, d_off, d_val, s);
+            if (C->trace && nnz > ZCHUNK) {
+                TD_HIP(hipStreamSynchronize(s));
+                std::fprintf(stderr, "[tdbem] coefficients %lld / %lld\n", (long long)std::min(nnz, c0 + ZCHUNK),
+                             (long long)nnz);
+            }
+        }
+    }
     // ---- Z0 = Zt^(1): pairs whose range starts at g = 1
     std::vector<int64_t> z0idx;
     std::vector<int> z0ptr(ne + 1, 0), z0col;
@@ -581,6 +594,8 @@ static void setup_impl(const tdbem_mesh *mesh, const tdbem_config *cfg, tdbem_ct
             p = pe;
         }
     }
+    if (C->trace) std::fprintf(stderr, "[tdbem] near-field store: %lld pairs, %lld values\n", (long long)nj.size(),
+                               (long long)nnz2);
     TD_REQUIRE(L <= 512, TDBEM_EINVAL, "near-field lag strips longer than 512 steps");
     std::vector<int> nl((size_t)ne * std::max(L, 1), 0);
     for (int i = 0; i < ne; ++i)

@@ -34,10 +34,11 @@ __global__ void k_lag_range(GeoDev G, int64_t npairs, const int *pi, const int *
 }
 
 // one thread per stored coefficient: pair found by binary search on offsets
-__global__ void k_zfill(GeoDev G, int64_t nnz, int64_t npairs, const int *pi, const int *pj,
+__global__ void k_zfill(GeoDev G, int64_t n, int64_t k0, int64_t npairs, const int *pi, const int *pj,
                         const int *g0, const int64_t *off, double *val) {
-    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nnz) return;
+    // coefficients k0 .. k0 + n - 1 of the pair-major store
+    int64_t k = k0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= k0 + n) return;
     int64_t lo = 0, hi = npairs - 1;
     while (lo < hi) {
         int64_t mid = (lo + hi + 1) >> 1;
@@ -54,11 +55,12 @@ void launch_lag_range(const GeoDev &G, int64_t npairs, const int *pi, const int 
     TD_HIP(hipGetLastError());
 }
 
-void launch_zfill(const GeoDev &G, int64_t nnz, int64_t npairs, const int *pi, const int *pj, const int *g0,
+void launch_zfill(const GeoDev &G, int64_t n, int64_t k0, int64_t npairs, const int *pi, const int *pj, const int *g0,
                   const int64_t *off, double *val, hipStream_t s) {
-    if (nnz <= 0) return;
+    if (n <= 0) return;
     int bs = 128;
-    hipLaunchKernelGGL(k_zfill, dim3((unsigned)((nnz + bs - 1) / bs)), dim3(bs), 0, s, G, nnz, npairs, pi, pj, g0, off, val);
+    hipLaunchKernelGGL(k_zfill, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, G, n, k0, npairs, pi, pj, g0, off,
+                       val);
     TD_HIP(hipGetLastError());
 }
 
