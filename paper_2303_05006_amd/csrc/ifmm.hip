@@ -488,21 +488,29 @@ __global__ void __launch_bounds__(256) k_p2m(const int *leaf_cells, const int *e
         __syncthreads();
         for (int q = threadIdx.x; q < NCH * NS; q += blockDim.x) {
             const int c = q / NS, b = q % NS;
+            // every variant from one load of each weight (per (v, n) the sum
+            // over j in the same order)
+            double a[NV_MAX][P];
+#pragma unroll
+            for (int v = 0; v < NV_MAX; ++v)
+#pragma unroll
+                for (int n = 0; n < P; ++n) a[v][n] = 0.0;
+            for (int j = 0; j < nj; ++j) {
+                const double w = Wm[(size_t)(jb + j) * NCH * NS + q];
+#pragma unroll
+                for (int v = 0; v < NV_MAX; ++v) {
+                    if (v >= NV) break;
+#pragma unroll
+                    for (int n = 0; n < P; ++n) a[v][n] += w * T[j][v][n];
+                }
+            }
 #pragma unroll
             for (int v = 0; v < NV_MAX; ++v) {
                 if (v >= NV) continue;
-                double a[P];
-#pragma unroll
-                for (int n = 0; n < P; ++n) a[n] = 0.0;
-                for (int j = 0; j < nj; ++j) {
-                    const double w = Wm[(size_t)(jb + j) * NCH * NS + q];
-#pragma unroll
-                    for (int n = 0; n < P; ++n) a[n] += w * T[j][v][n];
-                }
                 const size_t oi = ((((size_t)cell * WR + slot) * NV + v) * NCH + c) * nrhs * NN + (size_t)r * NN + b * P;
                 double *o = MM + oi;
 #pragma unroll
-                for (int n = 0; n < P; ++n) o[n] = jb == e0 ? a[n] : o[n] + a[n];
+                for (int n = 0; n < P; ++n) o[n] = jb == e0 ? a[v][n] : o[n] + a[v][n];
                 if (jb + 64 >= e1) reduced_copy<P>(o, MMf, MMh, oi);      // the last chunk: final values
             }
         }
@@ -599,11 +607,25 @@ template <int P>
 __global__ void __launch_bounds__(256) k_m2l_reduce(int n, const int *il_off, const double *YB, int ng,
                                                     size_t gstride, const double *PEND, int parity, double *LC) {
     constexpr int NN = Dim<P>::NN;
+    constexpr int QU = 8;              // entries whose loads are issued together (one lag group)
     int O = blockIdx.x, c = blockIdx.y;
+    const int q0 = il_off[O], q1 = il_off[O + 1];
     for (int v = threadIdx.x; v < NN; v += 256) {
         double s = PEND[(((size_t)O * 2 + parity) * NCH + c) * NN + v];
-        for (int q = il_off[O]; q < il_off[O + 1]; ++q)
-            for (int g = 0; g < ng; ++g) s += YB[g * gstride + ((size_t)q * NCH + c) * NN + v];
+        const double *y = YB + ((size_t)q0 * NCH + c) * NN + v;
+        int q = q0;
+        if (ng == 1) {
+            // the same additions in the same order, QU loads in flight
+            for (; q + QU <= q1; q += QU, y += (size_t)QU * NCH * NN) {
+                double t[QU];
+#pragma unroll
+                for (int u = 0; u < QU; ++u) t[u] = y[(size_t)u * NCH * NN];
+#pragma unroll
+                for (int u = 0; u < QU; ++u) s += t[u];
+            }
+        }
+        for (; q < q1; ++q, y += (size_t)NCH * NN)
+            for (int g = 0; g < ng; ++g) s += y[g * gstride];
         LC[((size_t)O * NCH + c) * NN + v] = s;
     }
 }
